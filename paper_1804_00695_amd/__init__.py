@@ -1,0 +1,204 @@
+"""MI355X (gfx950) two-phase SpGEMM with HBM / pinned-host chunking.
+
+Thin Python layer over the C ABI in include/mlspgemm.h: it allocates device
+memory and workspaces with PyTorch, passes raw pointers and the current HIP
+stream, and maps status codes to exceptions. Every step of the computation
+runs in the HIP library (libmlspgemm.so); there is no CPU fallback -- if the
+library is missing, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import CsrT, SpgemmError, check
+
+lib = _abi.load()
+
+__all__ = ["DeviceCsr", "HostCsr", "lib", "SpgemmError", "Workspace", "set_option", "get_option",
+           "row_work", "compress", "symbolic", "numeric", "spgemm", "stream_handle"]
+
+
+def stream_handle(stream: Optional[torch.cuda.Stream] = None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def set_option(opt: int, value: int):
+    check(lib.spgemm_set_option(opt, value), "spgemm_set_option")
+
+
+def get_option(opt: int) -> int:
+    return lib.spgemm_get_option(opt)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None or t.numel() == 0 else t.data_ptr()
+
+
+@dataclass
+class DeviceCsr:
+    """CSR matrix in device memory (int32 indices, fp64 values or None)."""
+    nrows: int
+    ncols: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    values: Optional[torch.Tensor]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    def handle(self) -> CsrT:
+        return CsrT(self.nrows, self.ncols, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.values))
+
+    @classmethod
+    def from_host(cls, M, device="cuda", values: bool = True) -> "DeviceCsr":
+        """From any object with nrows, ncols, row_ptr, col_idx, values (numpy)."""
+        rp = torch.from_numpy(np.ascontiguousarray(M.row_ptr, dtype=np.int32)).to(device)
+        ci = torch.from_numpy(np.ascontiguousarray(M.col_idx, dtype=np.int32)).to(device)
+        v = None
+        if values and getattr(M, "values", None) is not None:
+            v = torch.from_numpy(np.ascontiguousarray(M.values, dtype=np.float64)).to(device)
+        return cls(int(M.nrows), int(M.ncols), rp, ci, v)
+
+    def numpy(self):
+        v = None if self.values is None else self.values.cpu().numpy()
+        return self.row_ptr.cpu().numpy(), self.col_idx.cpu().numpy(), v
+
+
+@dataclass
+class HostCsr:
+    """CSR matrix in pinned host memory (the slow tier of the chunked path)."""
+    nrows: int
+    ncols: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    values: Optional[torch.Tensor]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    def handle(self) -> CsrT:
+        return CsrT(self.nrows, self.ncols, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.values))
+
+    @classmethod
+    def from_host(cls, M, values: bool = True) -> "HostCsr":
+        def pin(a, dt):
+            t = torch.empty(len(a), dtype=dt, pin_memory=True)
+            t.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+            return t
+        rp = pin(np.asarray(M.row_ptr, dtype=np.int32), torch.int32)
+        ci = pin(np.asarray(M.col_idx, dtype=np.int32), torch.int32)
+        v = None
+        if values and getattr(M, "values", None) is not None:
+            v = pin(np.asarray(M.values, dtype=np.float64), torch.float64)
+        return cls(int(M.nrows), int(M.ncols), rp, ci, v)
+
+
+class Workspace:
+    """A 256-byte aligned device scratch buffer, grown on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+        self.nbytes = 0
+
+    def get(self, nbytes: int) -> int:
+        if self.buf is None or self.nbytes < nbytes:
+            self.buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+            self.nbytes = int(nbytes)
+        p = self.buf.data_ptr()
+        return (p + 255) & ~255
+
+
+_default_ws = {}
+
+
+def _ws(ws: Optional[Workspace], device) -> Workspace:
+    if ws is not None:
+        return ws
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    key = str(d)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def workspace_size(A: DeviceCsr, B: DeviceCsr) -> int:
+    n = ctypes.c_size_t(0)
+    check(lib.spgemm_workspace_size(ctypes.byref(A.handle()), ctypes.byref(B.handle()), ctypes.byref(n)),
+          "spgemm_workspace_size")
+    return n.value
+
+
+def row_work(A: DeviceCsr, B: DeviceCsr, ws: Optional[Workspace] = None):
+    """Per-row multiply-add counts (int32 tensor) and their int64 total."""
+    dev = A.row_ptr.device
+    w = _ws(ws, dev)
+    nb = workspace_size(A, B)
+    out = torch.empty(max(A.nrows, 1), dtype=torch.int32, device=dev)
+    tot = ctypes.c_int64(0)
+    check(lib.spgemm_row_work(ctypes.byref(A.handle()), ctypes.byref(B.handle()), out.data_ptr(),
+                              ctypes.byref(tot), w.get(nb), nb, stream_handle()), "spgemm_row_work")
+    return out[:A.nrows], tot.value
+
+
+def compress(B: DeviceCsr):
+    """Compressed rows of B: (words uint32 [2*nnz] as int32 tensor, count int32 [nrows])."""
+    dev = B.row_ptr.device
+    words = torch.empty(max(2 * B.nnz, 2), dtype=torch.int32, device=dev)
+    count = torch.empty(max(B.nrows, 1), dtype=torch.int32, device=dev)
+    check(lib.spgemm_compress(ctypes.byref(B.handle()), words.data_ptr(), count.data_ptr(), None, 0,
+                              stream_handle()), "spgemm_compress")
+    return words[:2 * B.nnz], count[:B.nrows]
+
+
+def symbolic(A: DeviceCsr, B: DeviceCsr, ws: Optional[Workspace] = None, with_values: bool = True) -> DeviceCsr:
+    """Symbolic phase: structure of C = A*B (count pass, allocation, fill pass)."""
+    dev = A.row_ptr.device
+    w = _ws(ws, dev)
+    nb = workspace_size(A, B)
+    p = w.get(nb)
+    crp = torch.empty(A.nrows + 1, dtype=torch.int32, device=dev)
+    nnz = ctypes.c_int64(0)
+    ha, hb = A.handle(), B.handle()
+    s = stream_handle()
+    check(lib.spgemm_symbolic(ctypes.byref(ha), ctypes.byref(hb), crp.data_ptr(), None, ctypes.byref(nnz), p, nb, s),
+          "spgemm_symbolic(count)")
+    cci = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+    check(lib.spgemm_symbolic(ctypes.byref(ha), ctypes.byref(hb), crp.data_ptr(), cci.data_ptr(), None, p, nb, s),
+          "spgemm_symbolic(fill)")
+    vals = torch.empty(max(nnz.value, 1), dtype=torch.float64, device=dev) if with_values else None
+    return DeviceCsr(A.nrows, B.ncols, crp, cci[:nnz.value], None if vals is None else vals[:nnz.value])
+
+
+def numeric(A: DeviceCsr, B: DeviceCsr, C: DeviceCsr, ws: Optional[Workspace] = None) -> DeviceCsr:
+    """Numeric phase: fills C.values on C's structure."""
+    dev = A.row_ptr.device
+    w = _ws(ws, dev)
+    nb = workspace_size(A, B)
+    if C.values is None:
+        C.values = torch.empty(C.nnz, dtype=torch.float64, device=dev)
+    check(lib.spgemm_numeric(ctypes.byref(A.handle()), ctypes.byref(B.handle()), ctypes.byref(C.handle()),
+                             w.get(nb), nb, stream_handle()), "spgemm_numeric")
+    return C
+
+
+def check_errors(ws: Optional[Workspace] = None, device="cuda"):
+    w = _ws(ws, device)
+    check(lib.spgemm_check_errors(w.get(0), w.nbytes, stream_handle()), "spgemm_check_errors")
+
+
+def spgemm(A: DeviceCsr, B: DeviceCsr, ws: Optional[Workspace] = None) -> DeviceCsr:
+    """C = A*B, both phases."""
+    C = symbolic(A, B, ws)
+    return numeric(A, B, C, ws)

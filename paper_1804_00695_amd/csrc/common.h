@@ -1,0 +1,202 @@
+// common.h -- device-side descriptors and helpers shared by the gfx950 kernels.
+//
+// Every kernel works on a *batch* of independent products C_t = A_t * B_t
+// (a single product is a batch of one). Rows of all A_t are numbered in one
+// global row space: product t owns global rows [abase[t], abase[t+1]).
+// The same holds for the rows of all B_t (bbase). A row-range restriction
+// (k_lo, k_hi) and array offsets let the same kernels run on chunk parts
+// (the row-range fused multiply-add kernel of the chunking algorithms).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mls {
+
+constexpr int kWG = 256;          // threads per workgroup
+constexpr int kWave = 64;         // gfx950 wavefront
+constexpr int kXcd = 8;           // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr int kNumBins = 5;       // 3 LDS classes, spill, empty
+constexpr int kBinSpill = 3;
+constexpr int kBinEmpty = 4;
+
+// Error bits (device flag).
+constexpr uint32_t kErrBadCsr = 1u;
+constexpr uint32_t kErrOverflow = 2u;
+constexpr uint32_t kErrStructure = 4u;
+constexpr uint32_t kErrTable = 8u;
+
+// LDS capacities (hash slots) of the three classes, per phase. A row goes to
+// the first class whose threshold holds; beyond class 2 it spills.
+//   count  : threshold on the word upper bound u, table = u slots at most
+//   fill / numeric / tc : threshold on the exact size n, table >= 2n slots
+constexpr int kCountCap[3] = {512, 2048, 8192};
+constexpr int kFillCap[3] = {256, 1024, 4096};
+
+struct Prob {
+    // A (or an A/C row part): row pointers hold global entry offsets; the
+    // local entry index is row_ptr value - a_off.
+    const int32_t *arp;
+    const int32_t *aci;
+    const double *aval;
+    // B (or a B row part): local row = k - k_lo; local entry = brp - b_off.
+    const int32_t *brp;
+    const int32_t *bci;
+    const double *bval;
+    // Compressed B pattern, padded layout: row k's words at bw[brp[k]-b_off ...].
+    uint2 *bw;
+    int32_t *bwc;
+    // C: row pointers with offset c_off.
+    int32_t *crp;
+    int32_t *cci;
+    double *cval;
+    int32_t nrows;   // rows of A / C
+    int32_t ncols;   // columns of B / C
+    int32_t krows;   // rows of B held (k_hi - k_lo)
+    int32_t a_off, b_off, c_off;
+    int32_t k_lo, k_hi;     // A columns outside [k_lo, k_hi) are skipped
+    int32_t accumulate;     // numeric: 1 = add onto the values already in C
+    int32_t pad;
+};
+
+static_assert(sizeof(Prob) % 16 == 0, "Prob is copied in 16-byte words");
+
+struct Batch {
+    const Prob *probs;      // device array [nprob] (used when nprob > 1)
+    Prob p0;                // the product when nprob == 1
+    const int32_t *abase;   // device [nprob + 1]
+    const int32_t *bbase;   // device [nprob + 1]
+    int32_t nprob;
+    int32_t na;             // total A rows
+    int32_t nb;             // total B rows
+    int32_t pad;
+};
+
+// Per-phase device state inside the workspace.
+struct Sched {
+    uint32_t *err;
+    int32_t *bin_count;     // [kNumBins]
+    int32_t *bin_cursor;    // [kNumBins]
+    int32_t *task_cursor;   // [kNumBins * kXcd]
+    int32_t *val;           // per global row: size used for binning / result
+    uint8_t *cls;           // per global row: bin
+    int32_t *perm;          // rows grouped by bin
+};
+
+// Pointers read out of descriptors are generic; loads through them compile
+// to flat instructions, which make the compiler wait on LDS and vector memory
+// together. Every kernel therefore casts them to the global address space.
+#define MLS_G __attribute__((address_space(1)))
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ __forceinline__ const MLS_G T *gp(const T *p)
+{
+    return (const MLS_G T *)(p);
+}
+
+template <class T>
+__device__ __forceinline__ MLS_G T *gpw(T *p)
+{
+    return (MLS_G T *)(p);
+}
+
+__device__ __forceinline__ int find_prob(const int32_t *base, int nprob, int g)
+{
+    // largest t with base[t] <= g
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (gp(base)[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The descriptor of product t by value: from the kernel arguments for a
+// single product, from global memory for a batch.
+__device__ __forceinline__ Prob get_prob(const Batch &b, int t)
+{
+    if (b.nprob == 1) return b.p0;
+    Prob P;
+    const MLS_G u32x4 *src = (const MLS_G u32x4 *)(b.probs + t);
+    u32x4 *dst = (u32x4 *)&P;
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(Prob) / 16); ++w) dst[w] = src[w];
+    return P;
+}
+
+// Multiplicative (Fibonacci) hashing of a 32-bit key into 2^logcap slots.
+__device__ __forceinline__ uint32_t hslot(uint32_t key, int logcap)
+{
+    return (key * 0x9E3779B1u) >> (32 - logcap);
+}
+
+__device__ __forceinline__ int ilog2_ceil(int x)
+{
+    return x <= 1 ? 0 : 32 - __clz(x - 1);
+}
+
+// Sum over the G consecutive lanes of a group (G a power of two <= 64).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// Bin start = exclusive prefix of the bin counts.
+__device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
+{
+    int s = 0;
+    for (int c = 0; c < bin; ++c) s += bin_count[c];
+    return s;
+}
+
+// Per-wave dynamic task fetch. Tasks of a bin are split into one contiguous
+// slab per XCD (workgroup w runs on XCD w % 8), so neighbouring rows -- which
+// share rows of B -- are processed by CUs sharing one L2. A wave takes
+// `chunk` consecutive tasks per atomic (about 16 grabs per wave over the
+// bin), drains its own XCD's slab and then helps the others. Returns -1 when
+// all are done. Must be called by all lanes of the wave (uniform control).
+struct TaskIter {
+    int xcd;
+    int probe;   // how many slabs tried
+    int cur, end;
+    int chunk;
+};
+
+__device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg)
+{
+    TaskIter it;
+    it.xcd = (int)(blockIdx.x % kXcd);
+    it.probe = 0;
+    it.cur = it.end = 0;
+    int64_t waves = (int64_t)gridDim.x * waves_per_wg;
+    int64_t c = ntasks / (waves * 16);
+    it.chunk = (int)(c < 1 ? 1 : (c > 256 ? 256 : c));
+    return it;
+}
+
+__device__ __forceinline__ int next_task_wave(int32_t *cursor, int ntasks, TaskIter &it)
+{
+    if (it.cur < it.end) return it.cur++;
+    while (it.probe < kXcd) {
+        int x = (it.xcd + it.probe) & (kXcd - 1);
+        int lo = (int)(((int64_t)ntasks * x) / kXcd);
+        int hi = (int)(((int64_t)ntasks * (x + 1)) / kXcd);
+        int t = 0;
+        if ((threadIdx.x & (kWave - 1)) == 0) t = atomicAdd(cursor + x, it.chunk);
+        t = __shfl(t, 0, kWave);
+        if (lo + t < hi) {
+            it.cur = lo + t;
+            it.end = min(hi, lo + t + it.chunk);
+            return it.cur++;
+        }
+        ++it.probe;
+    }
+    return -1;
+}
+
+}  // namespace mls

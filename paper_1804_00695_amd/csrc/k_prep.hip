@@ -1,0 +1,351 @@
+// k_prep.hip -- kernels around the two phases: CSR checks, column compression
+// of B, per-row work estimate and binning, the row-pointer scan.
+#include "common.h"
+#include "launch.h"
+#include "profile.h"
+
+namespace mls {
+
+// ---------------------------------------------------------------------------
+// state reset (a fill kernel instead of hipMemsetAsync so that a captured
+// graph replays it faithfully)
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, double v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// CSR checks over the A rows (which = 0) or B rows (which = 1) of a batch:
+// row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, columns in range and
+// strictly increasing.
+
+__global__ void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int total = which == 0 ? b.na : b.nb;
+    if (g >= total) return;
+    const int32_t *base = which == 0 ? b.abase : b.bbase;
+    int t = b.nprob == 1 ? 0 : find_prob(base, b.nprob, g);
+    const Prob P = get_prob(b, t);
+    int i = g - (b.nprob == 1 ? 0 : gp(base)[t]);
+    const MLS_G int32_t *rp = gp(which == 0 ? P.arp : P.brp);
+    const MLS_G int32_t *ci = gp(which == 0 ? P.aci : P.bci);
+    int off = which == 0 ? P.a_off : P.b_off;
+    int ncols = which == 0 ? P.k_hi : P.ncols;
+    int nrows = which == 0 ? P.nrows : P.krows;
+    bool bad = false;
+    const int64_t nnz = gp(nnz_tab)[2 * t + which];
+    int s = rp[i], e = rp[i + 1];
+    if (i == 0 && s != off) bad = true;
+    if (i == nrows - 1 && (int64_t)e - off != nnz) bad = true;
+    // never read column indices outside [0, nnz)
+    if (e < s || s < off || (int64_t)e - off > nnz) bad = true;
+    if (!bad) {
+        int prev = -1;
+        for (int q = s - off; q < e - off; ++q) {
+            int c = ci[q];
+            if (c < 0 || c >= ncols || c <= prev) { bad = true; break; }
+            prev = c;
+        }
+    }
+    if (bad) atomicOr(err, kErrBadCsr);
+}
+
+// ---------------------------------------------------------------------------
+// Column compression of every B row (set = col >> 5, mask bit = col & 31),
+// padded layout: the words of row k start at B's entry offset of row k.
+
+__global__ void k_compress(Batch b)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.nb) return;
+    int t = b.nprob == 1 ? 0 : find_prob(b.bbase, b.nprob, g);
+    const Prob P = get_prob(b, t);
+    int k = g - (b.nprob == 1 ? 0 : gp(b.bbase)[t]);
+    int s = gp(P.brp)[k] - P.b_off, e = gp(P.brp)[k + 1] - P.b_off;
+    MLS_G u32x2 *__restrict__ out = (MLS_G u32x2 *)P.bw + s;
+    const MLS_G int32_t *__restrict__ bci = gp(P.bci);
+    int n = 0;
+    uint32_t cur = 0xffffffffu, mask = 0;
+    for (int q = s; q < e; ++q) {
+        uint32_t c = (uint32_t)bci[q];
+        uint32_t set = c >> 5;
+        if (set != cur) {
+            if (cur != 0xffffffffu) { u32x2 w; w.x = cur; w.y = mask; out[n++] = w; }
+            cur = set;
+            mask = 0;
+        }
+        mask |= 1u << (c & 31u);
+    }
+    if (cur != 0xffffffffu) { u32x2 w; w.x = cur; w.y = mask; out[n++] = w; }
+    gpw(P.bwc)[k] = n;
+}
+
+// ---------------------------------------------------------------------------
+// Row sizes and bins.
+//   kModeCount  : size = sum over in-range k of the word count of B_k (an
+//                 upper bound of the distinct column sets of row i of C)
+//   kModeFill   : size = min(that bound, nnz(C_i))
+//   kModeNumeric: size = nnz(C_i)
+//   kModeWork   : size = sum over in-range k of nnz(B_k) (multiply-adds)
+// Threshold classes: kCountCap for count, kFillCap/2 for fill and numeric.
+
+__device__ __forceinline__ int class_of(int mode, int64_t size, int force_spill)
+{
+    if (size == 0) return kBinEmpty;
+    if (force_spill) return kBinSpill;
+    if (mode == kModeCount) {
+        for (int c = 0; c < 3; ++c)
+            if (size <= kCountCap[c]) return c;
+    } else {
+        for (int c = 0; c < 3; ++c)
+            if (size <= kFillCap[c] / 2) return c;
+    }
+    return kBinSpill;
+}
+
+__global__ void k_bin(Batch b, int mode, Sched sc, int force_spill, unsigned long long *total)
+{
+    __shared__ int cnt[kNumBins];
+    __shared__ unsigned long long tsum;
+    if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) tsum = 0;
+    __syncthreads();
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < b.na) {
+        int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+        const Prob P = get_prob(b, t);
+        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        int64_t size = 0;
+        int64_t nc = 0;
+        if (mode != kModeWork && mode != kModeCount) nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
+        if (mode != kModeNumeric) {
+            const MLS_G int32_t *__restrict__ aci = gp(P.aci);
+            const MLS_G int32_t *__restrict__ brp = gp(P.brp);
+            const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
+            const int k_lo = P.k_lo, k_hi = P.k_hi;
+            int s = gp(P.arp)[i] - P.a_off, e = gp(P.arp)[i + 1] - P.a_off;
+            for (int p = s; p < e; ++p) {
+                int k = aci[p];
+                if (k < k_lo || k >= k_hi) continue;
+                int kl = k - k_lo;
+                if (mode == kModeWork) size += brp[kl + 1] - brp[kl];
+                else size += bwc[kl];
+            }
+        }
+        if (mode == kModeFill) size = size < nc ? size : nc;
+        if (mode == kModeNumeric) size = nc;
+        int c;
+        if (mode == kModeWork) {
+            c = kBinEmpty;
+            if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
+            atomicAdd(&tsum, (unsigned long long)size);
+        } else {
+            c = class_of(mode, size, force_spill);
+            if (size >= 0x7fffffffLL) size = 0x7fffffff;
+        }
+        gpw(sc.val)[g] = (int32_t)size;
+        gpw(sc.cls)[g] = (uint8_t)c;
+        atomicAdd(&cnt[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(sc.bin_count + threadIdx.x, cnt[threadIdx.x]);
+    if (threadIdx.x == 0 && total && tsum) atomicAdd(total, tsum);
+}
+
+// Group the rows by bin: perm[bin_start[c] + ...] = global row. Rows of one
+// workgroup (256 consecutive rows) stay together, so neighbouring rows are
+// processed close in time.
+__global__ void k_scatter(int na, Sched sc)
+{
+    __shared__ int cnt[kNumBins];
+    __shared__ int base[kNumBins];
+    if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = -1, pos = 0;
+    if (g < na) {
+        c = gp(sc.cls)[g];
+        pos = atomicAdd(&cnt[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumBins) {
+        int n = cnt[threadIdx.x];
+        base[threadIdx.x] = n ? atomicAdd(sc.bin_cursor + threadIdx.x, n) + bin_start(sc.bin_count, threadIdx.x) : 0;
+    }
+    __syncthreads();
+    if (c >= 0) gpw(sc.perm)[base[c] + pos] = g;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the per-row counts into int64 prefixes, then the int32
+// row pointers of each product.
+
+constexpr int kScanTile = 2048;   // rows per workgroup (8 per thread)
+
+__global__ void k_scan_tiles(const int32_t *val, int n, int64_t *tile_sum)
+{
+    __shared__ int64_t red[kWG / kWave];
+    int64_t s = 0;
+    int base = blockIdx.x * kScanTile;
+    for (int r = threadIdx.x; r < kScanTile; r += kWG) {
+        int g = base + r;
+        if (g < n) s += val[g];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kWG / kWave; ++w) t += red[w];
+        tile_sum[blockIdx.x] = t;
+    }
+}
+
+// One workgroup: exclusive scan of the tile sums in place.
+__global__ void k_scan_sums(int64_t *tile_sum, int ntiles)
+{
+    __shared__ int64_t part[kWG];
+    int per = (ntiles + kWG - 1) / kWG;
+    int lo = threadIdx.x * per, hi = min(ntiles, lo + per);
+    int64_t s = 0;
+    for (int i = lo; i < hi; ++i) s += tile_sum[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int w = 0; w < kWG; ++w) { int64_t v = part[w]; part[w] = run; run += v; }
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int i = lo; i < hi; ++i) { int64_t v = tile_sum[i]; tile_sum[i] = run; run += v; }
+}
+
+__global__ void k_scan_apply(const int32_t *val, int n, const int64_t *tile_off, int64_t *prefix)
+{
+    // 256 threads x 8 consecutive rows
+    __shared__ int64_t wsum[kWG / kWave];
+    int base = blockIdx.x * kScanTile + threadIdx.x * 8;
+    int64_t v[8];
+    int64_t s = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        int g = base + r;
+        v[r] = g < n ? val[g] : 0;
+        s += v[r];
+    }
+    // inclusive scan of s across the wave
+    int lane = threadIdx.x & 63;
+    int64_t incl = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int64_t off = tile_off[blockIdx.x];
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) off += wsum[w];
+    int64_t run = off + incl - s;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        int g = base + r;
+        if (g < n) prefix[g] = run;
+        run += v[r];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kWG - 1) prefix[n] = run;
+    if (base + 8 >= n && base < n) prefix[n] = run;
+}
+
+// Row pointers of every product from the global prefix; totals[t] = nnz(C_t).
+__global__ void k_write_rowptr(Batch b, const int64_t *prefix, int64_t *totals, uint32_t *err)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.na) return;
+    int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+    const Prob P = get_prob(b, t);
+    int r0 = b.nprob == 1 ? 0 : gp(b.abase)[t];
+    int i = g - r0;
+    int64_t v = prefix[g + 1] - prefix[r0];
+    if (v >= 0x7fffffffLL) { atomicOr(err, kErrOverflow); v = 0x7fffffff; }
+    gpw(P.crp)[i + 1] = (int32_t)v;
+    if (i == 0) gpw(P.crp)[0] = 0;
+    if (i == P.nrows - 1) totals[t] = prefix[g + 1] - prefix[r0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline int nblk(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int grid = nblk(n, kWG);
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid), dim3(kWG), 0, s, p, v, n);
+}
+
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return;
+    int grid = nblk(n, kWG);
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid), dim3(kWG), 0, s, p, v, n);
+}
+
+void launch_validate(const Batch &b, int which, const int64_t *nnz_tab, uint32_t *err, hipStream_t s)
+{
+    int n = which == 0 ? b.na : b.nb;
+    if (n <= 0) return;
+    ProfScope ps("validate", s);
+    hipLaunchKernelGGL(k_validate, dim3(nblk(n, kWG)), dim3(kWG), 0, s, b, which, nnz_tab, err);
+}
+
+void launch_compress(const Batch &b, hipStream_t s)
+{
+    if (b.nb <= 0) return;
+    ProfScope ps("compress", s);
+    hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kWG)), dim3(kWG), 0, s, b);
+}
+
+void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsigned long long *total,
+                hipStream_t s)
+{
+    if (b.na <= 0) return;
+    {
+        ProfScope ps("bin", s);
+        hipLaunchKernelGGL(k_bin, dim3(nblk(b.na, kWG)), dim3(kWG), 0, s, b, mode, sc, force_spill, total);
+    }
+    ProfScope ps("scatter", s);
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(b.na, kWG)), dim3(kWG), 0, s, b.na, sc);
+}
+
+int scan_tiles(int n) { return nblk(n > 0 ? n : 1, kScanTile); }
+
+void launch_scan(const int32_t *val, int n, int64_t *tile_sum, int64_t *prefix, hipStream_t s)
+{
+    int nt = scan_tiles(n);
+    ProfScope ps("scan", s);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kWG), 0, s, val, n, tile_sum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kWG), 0, s, tile_sum, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kWG), 0, s, val, n, tile_sum, prefix);
+}
+
+void launch_write_rowptr(const Batch &b, const int64_t *prefix, int64_t *totals, uint32_t *err, hipStream_t s)
+{
+    if (b.na <= 0) return;
+    ProfScope ps("write_rowptr", s);
+    hipLaunchKernelGGL(k_write_rowptr, dim3(nblk(b.na, kWG)), dim3(kWG), 0, s, b, prefix, totals, err);
+}
+
+}  // namespace mls

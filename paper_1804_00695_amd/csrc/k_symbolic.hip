@@ -1,0 +1,308 @@
+// k_symbolic.hip -- symbolic phase (Sec. 2.1): for every row i of C the union
+// of the compressed column sets of the rows B_k, k in row i of A.
+//
+// LDS path: G lanes own one row; the lanes walk the entries of row i of A
+// (one k per lane) and OR every (set, mask) word of compressed B_k into an
+// open-addressing hash table in LDS keyed by set. Count pass: rownnz =
+// sum of popcounts. Fill pass: the occupied (set, mask) pairs are compacted;
+// each pair's output offset is the popcount sum of the pairs with a smaller
+// set (so no sort is needed), and its bits expand into ascending columns.
+//
+// Spill path (rows whose word bound exceeds the largest LDS class): one
+// workgroup per row with a dense bitmap over all columns in global memory;
+// scanning the bitmap in order yields sorted columns directly.
+#include <cstdio>
+
+#include "common.h"
+#include "launch.h"
+#include "profile.h"
+
+namespace mls {
+
+constexpr uint32_t kEmptyKey = 0xffffffffu;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+constexpr int nw_for(int row_bytes, int rows_per_wave)
+{
+    int per_wave = row_bytes * rows_per_wave;
+    int nw = 65536 / per_wave;
+    return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
+}
+
+__device__ __forceinline__ void set_insert(uint32_t *key, uint32_t *msk, int logcap, uint32_t s, uint32_t m,
+                                           uint32_t *err)
+{
+    const uint32_t cmask = (1u << logcap) - 1u;
+    uint32_t h = hslot(s, logcap);
+    for (uint32_t probe = 0; probe <= cmask; ++probe) {
+        uint32_t k = __hip_atomic_load(key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == s) { atomicOr(msk + h, m); return; }
+        if (k == kEmptyKey) {
+            uint32_t old = atomicCAS(key + h, kEmptyKey, s);
+            if (old == kEmptyKey || old == s) { atomicOr(msk + h, m); return; }
+        }
+        h = (h + 1u) & cmask;
+    }
+    atomicOr(err, kErrTable);
+}
+
+template <int G, int CAP, bool FILL>
+__global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
+{
+    constexpr int W = kWave / G;
+    constexpr int ROWB = FILL ? CAP * 12 : CAP * 8;
+    constexpr int NW = nw_for(ROWB, W);
+    constexpr int LIST = FILL ? CAP / 2 : 1;
+    __shared__ uint32_t s_key[NW * W * CAP];
+    __shared__ uint32_t s_msk[NW * W * CAP];
+    __shared__ uint2 s_list[NW * W * LIST];
+    __shared__ int s_cnt[NW * W];
+
+    const int wave = threadIdx.x >> 6;
+    if (wave >= NW) return;   // launched with NW waves; guard anyway
+    const int lw = threadIdx.x & 63;
+    const int slot = lw / G, lane = lw % G;
+    const int rs = wave * W + slot;
+    uint32_t *key = s_key + rs * CAP;
+    uint32_t *msk = s_msk + rs * CAP;
+    uint2 *list = s_list + rs * LIST;
+
+    const MLS_G int32_t *perm = gp(sc.perm);
+    MLS_G int32_t *val = gpw(sc.val);
+    const int n_bin = gp(sc.bin_count)[bin];
+    const int start = bin_start(sc.bin_count, bin);
+    const int ntasks = (n_bin + W - 1) / W;
+    TaskIter it = task_iter(ntasks, NW);
+    for (;;) {
+        int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+        if (task < 0) break;
+        const int r = task * W + slot;
+        const bool active = r < n_bin;
+        int g = active ? perm[start + r] : 0;
+        int t = (!active || b.nprob == 1) ? 0 : find_prob(b.abase, b.nprob, g);
+        const Prob P = get_prob(b, t);
+        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        int size = active ? val[g] : 0;
+        int logcap = ilog2_ceil(FILL ? 2 * size : size);
+        if (logcap < 5) logcap = 5;
+        const int cap = 1 << logcap;
+        for (int h = lane; h < cap; h += G) { key[h] = kEmptyKey; msk[h] = 0u; }
+        if (lane == 0) s_cnt[rs] = 0;
+        wave_sync();
+        if (active) {
+            const MLS_G int32_t *__restrict__ aci = gp(P.aci);
+            const MLS_G int32_t *__restrict__ brp = gp(P.brp);
+            const MLS_G u32x2 *__restrict__ bw = (const MLS_G u32x2 *)P.bw;
+            const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
+            const int b_off = P.b_off, k_lo = P.k_lo, k_hi = P.k_hi;
+            int ps = gp(P.arp)[i] - P.a_off, pe = gp(P.arp)[i + 1] - P.a_off;
+            for (int p = ps + lane; p < pe; p += G) {
+                int k = aci[p];
+                if (k < k_lo || k >= k_hi) continue;
+                int kl = k - k_lo;
+                const MLS_G u32x2 *w = bw + (brp[kl] - b_off);
+                int nw = bwc[kl];
+                for (int x = 0; x < nw; ++x) {
+                    u32x2 wd = w[x];
+                    set_insert(key, msk, logcap, wd.x, wd.y, sc.err);
+                }
+            }
+        }
+        wave_sync();
+        if (!FILL) {
+            int c = 0;
+            for (int h = lane; h < cap; h += G) c += __popc(msk[h]);
+            c = group_sum<G>(c);
+            if (active && lane == 0) val[g] = c;
+        } else {
+            for (int h = lane; h < cap; h += G) {
+                uint32_t k = key[h];
+                if (k != kEmptyKey) {
+                    int e = atomicAdd(&s_cnt[rs], 1);
+                    if (e < LIST) list[e] = make_uint2(k, msk[h]);
+                    else atomicOr(sc.err, kErrTable);
+                }
+            }
+            wave_sync();
+            if (active) {
+                const int n = min(s_cnt[rs], LIST);
+                const int cs = gp(P.crp)[i] - P.c_off;
+                const int ce = gp(P.crp)[i + 1] - P.c_off;
+                MLS_G int32_t *__restrict__ cci = gpw(P.cci);
+                for (int e = lane; e < n; e += G) {
+                    uint2 me = list[e];
+                    int off = 0;
+                    for (int f = 0; f < n; ++f) {
+                        uint2 o = list[f];
+                        off += (o.x < me.x) ? __popc(o.y) : 0;
+                    }
+                    uint32_t m = me.y;
+                    int pos = cs + off;
+                    while (m) {
+                        int bit = __ffs(m) - 1;
+                        if (pos < ce) cci[pos] = (int32_t)(me.x * 32u + (uint32_t)bit);
+                        else atomicOr(sc.err, kErrStructure);
+                        ++pos;
+                        m &= m - 1u;
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+// Spill path: one workgroup per row, dense bitmap in global memory.
+__global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, uint32_t *bitmaps,
+                                                   int64_t words)
+{
+    __shared__ int s_red[kWG / kWave];
+    __shared__ int s_base;
+    uint32_t *bm = bitmaps + (int64_t)blockIdx.x * words;
+    const int n_bin = gp(sc.bin_count)[kBinSpill];
+    const int start = bin_start(sc.bin_count, kBinSpill);
+    for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
+        int g = gp(sc.perm)[start + r];
+        int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+        const Prob P = get_prob(b, t);
+        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        const int nwords = (P.ncols + 31) >> 5;
+        for (int w = threadIdx.x; w < nwords; w += kWG)
+            __hip_atomic_store(bm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        __syncthreads();
+        int ps = gp(P.arp)[i] - P.a_off, pe = gp(P.arp)[i + 1] - P.a_off;
+        for (int p = ps + threadIdx.x; p < pe; p += kWG) {
+            int k = gp(P.aci)[p];
+            if (k < P.k_lo || k >= P.k_hi) continue;
+            int kl = k - P.k_lo;
+            const MLS_G u32x2 *wv = (const MLS_G u32x2 *)P.bw + (gp(P.brp)[kl] - P.b_off);
+            int nw = gp(P.bwc)[kl];
+            for (int x = 0; x < nw; ++x) {
+                u32x2 wd = wv[x];
+                atomicOr(bm + wd.x, wd.y);
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if (!fill) {
+            int c = 0;
+            for (int w = threadIdx.x; w < nwords; w += kWG)
+                c += __popc(__hip_atomic_load(bm + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            c = group_sum<kWave>(c);
+            if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = c;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int s = 0;
+                for (int x = 0; x < kWG / kWave; ++x) s += s_red[x];
+                gpw(sc.val)[g] = s;
+            }
+            __syncthreads();
+        } else {
+            int cs = gp(P.crp)[i] - P.c_off;
+            MLS_G int32_t *cci = gpw(P.cci);
+            if (threadIdx.x == 0) s_base = 0;
+            __syncthreads();
+            for (int w0 = 0; w0 < nwords; w0 += kWG) {
+                int w = w0 + threadIdx.x;
+                uint32_t m = w < nwords ? __hip_atomic_load(bm + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+                int c = __popc(m);
+                // exclusive scan of c over the workgroup
+                int lane = threadIdx.x & 63;
+                int incl = c;
+                for (int o = 1; o < 64; o <<= 1) {
+                    int y = __shfl_up(incl, o, kWave);
+                    if (lane >= o) incl += y;
+                }
+                if (lane == 63) s_red[threadIdx.x >> 6] = incl;
+                __syncthreads();
+                int off = s_base;
+                for (int x = 0; x < (int)(threadIdx.x >> 6); ++x) off += s_red[x];
+                int pos = cs + off + incl - c;
+                const int ce = gp(P.crp)[i + 1] - P.c_off;
+                while (m) {
+                    int bit = __ffs(m) - 1;
+                    if (pos < ce) cci[pos] = w * 32 + bit;
+                    else atomicOr(sc.err, kErrStructure);
+                    ++pos;
+                    m &= m - 1u;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int s = 0;
+                    for (int x = 0; x < kWG / kWave; ++x) s += s_red[x];
+                    s_base += s;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename K>
+static int persistent_grid(K kernel, int threads)
+{
+    static int cus = device_cu_count();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+template <int G, int CAP, bool FILL>
+static void launch_sym_class(const Batch &b, const Sched &sc, int bin, hipStream_t s)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_for(FILL ? CAP * 12 : CAP * 8, W);
+    static int grid = persistent_grid(k_sym_lds<G, CAP, FILL>, NW * kWave);
+    static char name[64];
+    if (!name[0]) snprintf(name, sizeof(name), "sym_%s_lds_G%d_C%d", FILL ? "fill" : "count", G, CAP);
+    ProfScope ps(name, s);
+    hipLaunchKernelGGL((k_sym_lds<G, CAP, FILL>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
+}
+
+template <bool FILL>
+static void launch_sym_all(const Batch &b, const Sched &sc, int G, hipStream_t s)
+{
+    constexpr int C0 = FILL ? kFillCap[0] : kCountCap[0];
+    constexpr int C1 = FILL ? kFillCap[1] : kCountCap[1];
+    constexpr int C2 = FILL ? kFillCap[2] : kCountCap[2];
+    switch (G) {
+    case 8: launch_sym_class<8, C0, FILL>(b, sc, 0, s); break;
+    case 16: launch_sym_class<16, C0, FILL>(b, sc, 0, s); break;
+    case 64: launch_sym_class<64, C0, FILL>(b, sc, 0, s); break;
+    default: launch_sym_class<32, C0, FILL>(b, sc, 0, s); break;
+    }
+    if (G >= 64) launch_sym_class<64, C1, FILL>(b, sc, 1, s);
+    else launch_sym_class<32, C1, FILL>(b, sc, 1, s);
+    launch_sym_class<64, C2, FILL>(b, sc, 2, s);
+}
+
+void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, uint32_t *spill_bitmaps, int spill_slots,
+                     int64_t spill_words, hipStream_t s)
+{
+    if (b.na <= 0) return;
+    if (fill) launch_sym_all<true>(b, sc, G, s);
+    else launch_sym_all<false>(b, sc, G, s);
+    ProfScope ps(fill ? "sym_fill_spill" : "sym_count_spill", s);
+    hipLaunchKernelGGL(k_sym_spill, dim3(spill_slots), dim3(kWG), 0, s, b, sc, fill, spill_bitmaps, spill_words);
+}
+
+int device_cu_count()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+}  // namespace mls

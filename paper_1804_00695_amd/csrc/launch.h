@@ -1,0 +1,51 @@
+// launch.h -- host-side launchers of the gfx950 kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mls {
+
+enum { kModeCount = 0, kModeFill = 1, kModeNumeric = 2, kModeWork = 3 };
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void launch_validate(const Batch &b, int which, const int64_t *nnz_tab, uint32_t *err, hipStream_t s);
+void launch_compress(const Batch &b, hipStream_t s);
+void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsigned long long *total,
+                hipStream_t s);
+int scan_tiles(int n);
+void launch_scan(const int32_t *val, int n, int64_t *tile_sum, int64_t *prefix, hipStream_t s);
+void launch_write_rowptr(const Batch &b, const int64_t *prefix, int64_t *totals, uint32_t *err, hipStream_t s);
+
+// Symbolic phase: count (fill == 0) or fill (fill == 1) over the binned rows.
+// G = lanes per row for the LDS classes. spill_bitmaps: global scratch of
+// spill_slots bitmaps of spill_words 32-bit words each.
+void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, uint32_t *spill_bitmaps,
+                     int spill_slots, int64_t spill_words, hipStream_t s);
+
+// Numeric phase (row-range fused multiply-add) over the binned rows.
+void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s);
+
+// Triangle counting over the binned rows of L (A = B = L in the batch).
+void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long long *total,
+               uint32_t *spill_bitmaps, int spill_slots, int64_t spill_words, hipStream_t s);
+void launch_tc_bin(const Batch &b, const Sched &sc, hipStream_t s);
+
+// Backward (adjoint) over the binned rows of W (= pattern of C).
+void launch_backward(const Batch &b, const Sched &sc, const double *wval, double *dA, double *dB, int G,
+                     hipStream_t s);
+
+// Transpose and masked gather helpers.
+void launch_transpose(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *ci, const double *v,
+                      int32_t *trp, int32_t *tci, double *tv, int32_t *cursor, int64_t *tile_sum,
+                      int64_t *prefix, int32_t *cnt, hipStream_t s);
+void launch_mask_gather(int32_t nrows, const int32_t *xrp, const int32_t *xci, const double *xv,
+                        const int32_t *prp, const int32_t *pci, double *out, hipStream_t s);
+
+// Persistent grid sizes (workgroups) per kernel shape.
+int device_cu_count();
+
+}  // namespace mls

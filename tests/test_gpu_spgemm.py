@@ -1,0 +1,180 @@
+"""GPU parity of the two-phase product against the oracle (through the C ABI).
+
+Structure (row_ptr, col_idx) must be bit-exact; values within
+|c - c_ref| <= 1e-12 * sum|a||b| (the oracle's error scale), and -- because
+the kernels add the terms of each entry in ascending k with rounded products,
+as the oracle does -- also bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+mls = pytest.importorskip("paper_1804_00695_amd")
+TOL = 1e-12
+
+
+@pytest.fixture(autouse=True)
+def _reset_options():
+    yield
+    mls.set_option(mls._abi.OPT_FORCE_SPILL, 0)
+    mls.set_option(mls._abi.OPT_GROUP_SIZE, 0)
+    mls.set_option(mls._abi.OPT_VALIDATE, 1)
+
+
+def gpu_product(A, B):
+    dA, dB = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B)
+    C = mls.spgemm(dA, dB)
+    torch.cuda.synchronize()
+    mls.check_errors()
+    return C.numpy()
+
+
+def check(A, B, bitwise=True):
+    rp, ci, v = gpu_product(A, B)
+    R, cabs = oracle.spgemm(A, B)
+    assert np.array_equal(rp, R.row_ptr), "row_ptr differs"
+    assert np.array_equal(ci, R.col_idx), "col_idx differs"
+    if R.values is not None:
+        err = np.abs(v - R.values)
+        assert np.all(err <= TOL * cabs), float(np.max(err - TOL * cabs))
+        if bitwise:
+            assert np.array_equal(v, R.values)
+    return R
+
+
+def test_laplace2d_64_square():
+    A = synth.laplace2d_5pt(64)
+    R = check(A, A)
+    assert R.nnz == 51972
+
+
+@pytest.mark.parametrize("n,amp", [(2, 0.0), (5, 0.0), (12, 0.0), (12, 0.1), (21, 0.1)])
+def test_stencil27_square(n, amp):
+    A = synth.stencil27_3d(n, amp=amp, seed=2)
+    R = check(A, A)
+    assert R.nnz == (5 * n - 6) ** 3
+
+
+@pytest.mark.parametrize("shape", [(3000, 2000, 2500, 5.0, 7.0), (1000, 1000, 1000, 8.0, 8.0),
+                                   (777, 4099, 33, 3.0, 2.0), (1, 500, 300, 40.0, 9.0)])
+def test_poisson_rect(shape):
+    m, k, n, la, lb = shape
+    A = synth.poisson_csr(m, k, la, seed=m + 1)
+    B = synth.poisson_csr(k, n, lb, seed=k + 2)
+    check(A, B)
+
+
+def test_empty_rows_and_matrices():
+    A = synth.random_csr(300, 200, 0.05, 3, empty_rows=0.5)
+    B = synth.random_csr(200, 150, 0.05, 4, empty_rows=0.5)
+    check(A, B)
+    Z = synth.Csr(50, 40, np.zeros(51, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    W = synth.poisson_csr(40, 60, 3.0, 5)
+    check(Z, W)
+    check(synth.poisson_csr(30, 50, 3.0, 6), synth.Csr(50, 70, np.zeros(51, np.int32), np.zeros(0, np.int32), np.zeros(0)))
+
+
+def wide_rows(m, k, per_row, seed):
+    g = synth.rng(seed)
+    rows = [np.sort(g.choice(k, per_row, replace=False)) for _ in range(m)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    return synth.Csr(m, k, rp, np.concatenate(rows).astype(np.int32), g.standard_normal(int(rp[-1])))
+
+
+@pytest.mark.parametrize("per_row", [30, 120, 400, 1500])
+def test_large_rows_all_classes(per_row):
+    # nnz(C_i) ~ per_row * 8 spans the LDS classes and the global spill path
+    A = wide_rows(64, 6000, per_row, per_row)
+    B = synth.poisson_csr(6000, 20000, 8.0, 99)
+    check(A, B)
+
+
+@pytest.mark.parametrize("G", [8, 16, 32, 64])
+def test_forced_group_sizes(G):
+    mls.set_option(mls._abi.OPT_GROUP_SIZE, G)
+    check(synth.stencil27_3d(9, amp=0.1), synth.stencil27_3d(9, amp=0.1, seed=3))
+    check(synth.poisson_csr(500, 400, 6.0, 7), synth.poisson_csr(400, 450, 12.0, 8))
+
+
+def test_forced_spill_identical():
+    A = synth.stencil27_3d(8, amp=0.1)
+    mls.set_option(mls._abi.OPT_FORCE_SPILL, 1)
+    check(A, A)
+    check(synth.poisson_csr(300, 300, 5.0, 9), synth.poisson_csr(300, 400, 5.0, 10))
+
+
+def test_row_work_and_compress():
+    A = synth.poisson_csr(2000, 1500, 6.0, 21)
+    B = synth.poisson_csr(1500, 3000, 9.0, 22)
+    dA, dB = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B)
+    w, tot = mls.row_work(dA, dB)
+    ref = oracle.row_work(A, B)
+    assert np.array_equal(w.cpu().numpy(), ref) and tot == int(ref.sum())
+    words, count = mls.compress(dB)
+    words = words.cpu().numpy().view(np.uint32)
+    count = count.cpu().numpy()
+    rp, sets, masks = oracle.compress(B)
+    assert np.array_equal(count, np.diff(rp))
+    for k in range(B.nrows):
+        s = int(B.row_ptr[k])
+        got = words[2 * s: 2 * (s + count[k])]
+        assert np.array_equal(got[0::2], sets[rp[k]:rp[k + 1]].view(np.uint32))
+        assert np.array_equal(got[1::2], masks[rp[k]:rp[k + 1]])
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "duplicate", "out_of_range", "decreasing"])
+def test_device_validation(bad):
+    B = synth.poisson_csr(20, 30, 4.0, 1)
+    A = synth.poisson_csr(10, 20, 4.0, 2)
+    rp, ci = A.row_ptr.copy(), A.col_idx.copy()
+    r = int(np.argmax(np.diff(rp) >= 2))
+    s = int(rp[r])
+    if bad == "unsorted":
+        ci[s], ci[s + 1] = ci[s + 1], ci[s]
+    elif bad == "duplicate":
+        ci[s + 1] = ci[s]
+    elif bad == "out_of_range":
+        ci[s] = 25
+    else:
+        r = int(np.argmax(rp[1:-1] >= 1)) + 1     # a row r >= 1 with row_ptr[r] >= 1
+        rp[r + 1] = rp[r] - 1                     # still inside [0, nnz]
+    Abad = synth.Csr(A.nrows, A.ncols, rp, ci, A.values)
+    with pytest.raises(mls.SpgemmError, match="BAD_CSR"):
+        mls.symbolic(mls.DeviceCsr.from_host(Abad), mls.DeviceCsr.from_host(B))
+
+
+def test_dimension_mismatch():
+    A = synth.poisson_csr(10, 20, 4.0, 2)
+    B = synth.poisson_csr(21, 30, 4.0, 1)
+    with pytest.raises(mls.SpgemmError, match="DIM_MISMATCH"):
+        mls.symbolic(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B))
+
+
+def test_numeric_detects_missing_structure():
+    A = synth.poisson_csr(100, 80, 4.0, 31)
+    B = synth.poisson_csr(80, 90, 4.0, 32)
+    R, _ = oracle.spgemm(A, B)
+    # drop the last entry of the first non-empty row
+    r = int(np.argmax(np.diff(R.row_ptr) > 0))
+    keep = np.ones(R.nnz, bool)
+    keep[int(R.row_ptr[r + 1]) - 1] = False
+    rp = R.row_ptr.copy()
+    rp[r + 1:] -= 1
+    C = synth.Csr(R.nrows, R.ncols, rp, R.col_idx[keep], np.zeros(int(keep.sum())))
+    dA, dB, dC = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(C)
+    ws = mls.Workspace()
+    mls.numeric(dA, dB, dC, ws)
+    with pytest.raises(mls.SpgemmError, match="STRUCTURE"):
+        mls.check_errors(ws)
+
+
+def test_deterministic_repeat():
+    A = synth.stencil27_3d(14, amp=0.1)
+    r1 = gpu_product(A, A)
+    r2 = gpu_product(A, A)
+    for x, y in zip(r1, r2):
+        assert np.array_equal(x, y)
