@@ -202,3 +202,73 @@ def spgemm(A: DeviceCsr, B: DeviceCsr, ws: Optional[Workspace] = None) -> Device
     """C = A*B, both phases."""
     C = symbolic(A, B, ws)
     return numeric(A, B, C, ws)
+
+
+# ---------------------------------------------------------------------------
+# chunked execution (host pinned A, B, C; HBM budget)
+
+class Plan:
+    """Alg. "chunker" decision for one product (owns the C plan object)."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib.spgemm_plan_destroy(self._h)
+            self._h = None
+
+    @property
+    def info(self) -> dict:
+        inf = _abi.PlanInfo()
+        check(lib.spgemm_plan_info_get(self._h, ctypes.byref(inf)), "spgemm_plan_info_get")
+        return {f: getattr(inf, f) for f, _ in _abi.PlanInfo._fields_}
+
+    def parts(self, which: int):
+        n = self.info["n_ac_parts" if which == 0 else "n_b_parts"]
+        arr = np.zeros(2 * max(n, 1), dtype=np.int32)
+        check(lib.spgemm_plan_parts(self._h, which, arr.ctypes.data, n), "spgemm_plan_parts")
+        return [(int(arr[2 * i]), int(arr[2 * i + 1])) for i in range(n)]
+
+    def steps(self):
+        n = self.info["n_steps"]
+        arr = (_abi.PlanStep * max(n, 1))()
+        check(lib.spgemm_plan_steps(self._h, arr, n), "spgemm_plan_steps")
+        return [(s.kind, s.matrix, s.part, s.row_begin, s.row_end, int(s.bytes), s.slot) for s in arr[:n]]
+
+
+def chunked_plan(a_row_ptr, b_row_ptr, ncols_b: int, c_row_ptr, budget: int, nbuf: int = 2,
+                 min_parts: int = 1) -> Plan:
+    """Partition A/C and B into row parts for an HBM budget (host only, no GPU)."""
+    arp = np.ascontiguousarray(a_row_ptr, dtype=np.int32)
+    brp = np.ascontiguousarray(b_row_ptr, dtype=np.int32)
+    crp = np.ascontiguousarray(c_row_ptr, dtype=np.int32)
+    nA, nB = len(arp) - 1, len(brp) - 1
+    ha = CsrT(nA, nB, int(arp[-1]), arp.ctypes.data, None, None)
+    hb = CsrT(nB, ncols_b, int(brp[-1]), brp.ctypes.data, None, None)
+    out = ctypes.c_void_p(0)
+    check(lib.spgemm_chunked_plan(ctypes.byref(ha), ctypes.byref(hb), crp.ctypes.data, int(budget), nbuf, min_parts,
+                                  ctypes.byref(out)), "spgemm_chunked_plan")
+    return Plan(out.value, (arp, brp, crp))
+
+
+class ChunkStreams:
+    """Compute, host-to-device and device-to-host streams (default priority)."""
+
+    def __init__(self, device="cuda"):
+        self.compute = torch.cuda.current_stream(device)
+        self.h2d = torch.cuda.Stream(device)
+        self.d2h = torch.cuda.Stream(device)
+
+
+def numeric_chunked(A: HostCsr, B: HostCsr, C: HostCsr, plan: Plan, ws: Optional[Workspace] = None,
+                    streams: Optional[ChunkStreams] = None, device="cuda") -> HostCsr:
+    """Chunked numeric phase: C.values (pinned host) = A*B on C's structure."""
+    w = _ws(ws, device)
+    nb = plan.info["ws_bytes"]
+    st = streams or ChunkStreams(device)
+    check(lib.spgemm_numeric_chunked(ctypes.byref(A.handle()), ctypes.byref(B.handle()), ctypes.byref(C.handle()),
+                                     plan._h, w.get(nb), nb, st.compute.cuda_stream, st.h2d.cuda_stream,
+                                     st.d2h.cuda_stream), "spgemm_numeric_chunked")
+    return C

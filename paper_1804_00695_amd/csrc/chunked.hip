@@ -1,0 +1,267 @@
+// chunked.hip -- executor of the chunking algorithms (Sec. 3.3.1, Algs.
+// "chunk1" and "chunk2"): A, B and C live in pinned host memory (the slow
+// tier); row parts are copied into part buffers carved from the workspace
+// (the fast tier, HBM), multiplied by the row-range fused multiply-add
+// kernel (C_r += A_r[:, P_b] * B_b, Sec. 3.2.2) and copied back.
+//
+// Copies host->device go on s_h2d, device->host on s_d2h and kernels on
+// s_compute; events order them:
+//   - a part buffer is overwritten only after the kernel (and, for C, the
+//     copy back) that used its previous contents has finished;
+//   - a kernel starts after the copies of its A/C part and B part;
+//   - C's partial values are copied back in (Alg. chunk2, second B part on)
+//     only after every earlier copy back has finished.
+// With nbuf_inner = 2 the inner-loop matrix alternates between two buffers,
+// so its next copy overlaps the current kernel (double buffering). Every
+// B part is visited in ascending order and each kernel adds its terms in
+// ascending k, so the result is bit-identical to spgemm_numeric.
+#include <algorithm>
+#include <cstring>
+
+#include "../../include/mlspgemm.h"
+#include "common.h"
+#include "internal.h"
+#include "launch.h"
+#include "plan.h"
+#include "profile.h"
+
+using namespace mls;
+
+namespace {
+
+constexpr size_t kRegionSlack = 2048;
+
+inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct AcBuf {
+    char *base = nullptr;
+    int32_t r0 = 0, r1 = 0;
+    int32_t *arp = nullptr, *aci = nullptr, *crp = nullptr, *cci = nullptr;
+    double *aval = nullptr, *cval = nullptr;
+    int64_t nnz_c = 0;
+};
+
+struct BBuf {
+    char *base = nullptr;
+    int32_t r0 = 0, r1 = 0;
+    int32_t *brp = nullptr, *bci = nullptr;
+    double *bval = nullptr;
+};
+
+struct Ev {
+    hipEvent_t e = nullptr;
+    bool recorded = false;
+    hipError_t record(hipStream_t s)
+    {
+        recorded = true;
+        return hipEventRecord(e, s);
+    }
+    hipError_t wait(hipStream_t s) const { return recorded ? hipStreamWaitEvent(s, e, 0) : hipSuccess; }
+};
+
+void place_ac(AcBuf &b, const spgemm_csr *A, const spgemm_csr *C, int32_t r0, int32_t r1)
+{
+    b.r0 = r0;
+    b.r1 = r1;
+    const int64_t na = (int64_t)A->row_ptr[r1] - A->row_ptr[r0];
+    const int64_t nc = (int64_t)C->row_ptr[r1] - C->row_ptr[r0];
+    char *p = b.base;
+    b.arp = (int32_t *)p; p += al(4 * (size_t)(r1 - r0 + 1));
+    b.aci = (int32_t *)p; p += al(4 * (size_t)na);
+    b.aval = (double *)p; p += al(8 * (size_t)na);
+    b.crp = (int32_t *)p; p += al(4 * (size_t)(r1 - r0 + 1));
+    b.cci = (int32_t *)p; p += al(4 * (size_t)nc);
+    b.cval = (double *)p;
+    b.nnz_c = nc;
+}
+
+void place_b(BBuf &b, const spgemm_csr *B, int32_t r0, int32_t r1)
+{
+    b.r0 = r0;
+    b.r1 = r1;
+    const int64_t nb = (int64_t)B->row_ptr[r1] - B->row_ptr[r0];
+    char *p = b.base;
+    b.brp = (int32_t *)p; p += al(4 * (size_t)(r1 - r0 + 1));
+    b.bci = (int32_t *)p; p += al(4 * (size_t)nb);
+    b.bval = (double *)p;
+}
+
+}  // namespace
+
+namespace mls {
+
+spgemm_status numeric_launch(const Batch &b, double avg_b, char *ws, const Layout &L, hipStream_t s)
+{
+    Sched sc = make_sched(ws, L);
+    // clear the scheduling counters but keep the error word, so that errors
+    // of every part accumulate until the end of the chunked run
+    launch_fill_i32((int32_t *)(ws + L.hdr + kHdrBinCount), 0, (kHdrBytes - kHdrBinCount) / 4, s);
+    launch_bin(b, kModeNumeric, sc, (int)g_opt.force_spill, nullptr, s);
+    launch_numeric(b, sc, choose_group(avg_b), s);
+    return check_launch();
+}
+
+}  // namespace mls
+
+extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgemm_csr *B, spgemm_csr *C,
+                                                spgemm_plan *plan, void *ws_v, size_t ws_bytes, hipStream_t s_c,
+                                                hipStream_t s_h, hipStream_t s_d)
+{
+    if (!A || !B || !C || !plan || !ws_v) return SPGEMM_ERR_INVALID_ARG;
+    PlanImpl *P = reinterpret_cast<PlanImpl *>(plan);
+    if (A->nrows != P->nA || B->nrows != P->nB || B->ncols != P->ncols || C->nrows != A->nrows) return SPGEMM_ERR_DIM_MISMATCH;
+    if (A->ncols != B->nrows || C->ncols != B->ncols) return SPGEMM_ERR_DIM_MISMATCH;
+    if (!A->row_ptr || !B->row_ptr || !C->row_ptr) return SPGEMM_ERR_INVALID_ARG;
+    if ((A->nnz > 0 && (!A->col_idx || !A->values)) || (B->nnz > 0 && (!B->col_idx || !B->values)) ||
+        (C->nnz > 0 && (!C->col_idx || !C->values)))
+        return SPGEMM_ERR_INVALID_ARG;
+    if ((int64_t)ws_bytes < P->ws_bytes) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
+    if (((uintptr_t)ws_v & 255) != 0) return SPGEMM_ERR_INVALID_ARG;
+    char *ws = (char *)ws_v;
+
+    const Layout L = make_layout(1, A->nrows, B->nrows, 0, B->ncols, false);
+    char *buf0 = ws + al(L.total);
+    const size_t rac = al((size_t)P->max_ac) + kRegionSlack;
+    const size_t rb = al((size_t)P->max_b) + kRegionSlack;
+    AcBuf acb[2];
+    BBuf bb[2];
+    size_t need;
+    if (P->algo == 1) {
+        acb[0].base = buf0;
+        for (int s = 0; s < P->nbuf_inner; ++s) bb[s].base = buf0 + rac + s * rb;
+        need = al(L.total) + rac + P->nbuf_inner * rb;
+    } else {
+        bb[0].base = buf0;
+        for (int s = 0; s < P->nbuf_inner; ++s) acb[s].base = buf0 + rb + s * rac;
+        need = al(L.total) + rb + P->nbuf_inner * rac;
+    }
+    if (need > ws_bytes) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
+    reset_header(ws, L, s_c);
+
+    Ev ev_b_ready[2], ev_ac_ready[2], ev_kdone[2], ev_d2h[2], ev_outer_free, ev_last_kernel, ev_last_d2h;
+    Ev *all[] = {&ev_b_ready[0], &ev_b_ready[1], &ev_ac_ready[0], &ev_ac_ready[1], &ev_kdone[0], &ev_kdone[1],
+                 &ev_d2h[0], &ev_d2h[1], &ev_outer_free, &ev_last_kernel, &ev_last_d2h};
+    hipError_t e = hipSuccess;
+    for (Ev *x : all)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&x->e, hipEventDisableTiming);
+    auto cleanup = [&]() {
+        for (Ev *x : all)
+            if (x->e) hipEventDestroy(x->e);
+    };
+    if (e != hipSuccess) { cleanup(); return hip_fail(e); }
+
+    const double avg_b = B->nrows > 0 ? (double)B->nnz / B->nrows : 1.0;
+    int64_t issued_h = 0, issued_d = 0;
+    spgemm_status st = SPGEMM_OK;
+    auto h2d = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes == 0 || e != hipSuccess) return;
+        e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s_h);
+        issued_h += (int64_t)bytes;
+    };
+    auto d2h = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes == 0 || e != hipSuccess) return;
+        e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s_d);
+        issued_d += (int64_t)bytes;
+    };
+    const bool ac_outer = P->algo == 1;
+
+    for (const spgemm_plan_step &stp : P->steps) {
+        if (e != hipSuccess || st != SPGEMM_OK) break;
+        const int slot = stp.slot;
+        const int sac = ac_outer ? 0 : slot;   // buffer of the A/C part
+        const int sb = ac_outer ? slot : 0;    // buffer of the B part
+        const int32_t r0 = stp.row_begin, r1 = stp.row_end;
+        switch (stp.kind) {
+        case kStepH2D:
+            if (stp.matrix == kMatA) {
+                AcBuf &b = acb[sac];
+                e = ac_outer ? ev_outer_free.wait(s_h) : ev_d2h[sac].wait(s_h);
+                place_ac(b, A, C, r0, r1);
+                const int64_t a0 = A->row_ptr[r0], a1 = A->row_ptr[r1];
+                h2d(b.arp, A->row_ptr + r0, 4 * (size_t)(r1 - r0 + 1));
+                h2d(b.aci, A->col_idx + a0, 4 * (size_t)(a1 - a0));
+                h2d(b.aval, A->values + a0, 8 * (size_t)(a1 - a0));
+            } else if (stp.matrix == kMatCStruct) {
+                AcBuf &b = acb[sac];
+                const int64_t c0 = C->row_ptr[r0], c1 = C->row_ptr[r1];
+                h2d(b.crp, C->row_ptr + r0, 4 * (size_t)(r1 - r0 + 1));
+                h2d(b.cci, C->col_idx + c0, 4 * (size_t)(c1 - c0));
+                if (e == hipSuccess) e = ev_ac_ready[sac].record(s_h);
+            } else if (stp.matrix == kMatCVal) {
+                AcBuf &b = acb[sac];
+                if (e == hipSuccess) e = ev_last_d2h.wait(s_h);
+                const int64_t c0 = C->row_ptr[r0], c1 = C->row_ptr[r1];
+                h2d(b.cval, C->values + c0, 8 * (size_t)(c1 - c0));
+                if (e == hipSuccess) e = ev_ac_ready[sac].record(s_h);
+            } else {   // B part
+                BBuf &b = bb[sb];
+                e = ac_outer ? ev_kdone[sb].wait(s_h) : ev_last_kernel.wait(s_h);
+                place_b(b, B, r0, r1);
+                const int64_t q0 = B->row_ptr[r0], q1 = B->row_ptr[r1];
+                h2d(b.brp, B->row_ptr + r0, 4 * (size_t)(r1 - r0 + 1));
+                h2d(b.bci, B->col_idx + q0, 4 * (size_t)(q1 - q0));
+                h2d(b.bval, B->values + q0, 8 * (size_t)(q1 - q0));
+                if (e == hipSuccess) e = ev_b_ready[sb].record(s_h);
+            }
+            break;
+        case kStepZero: {
+            AcBuf &b = acb[sac];
+            e = ac_outer ? ev_outer_free.wait(s_c) : ev_d2h[sac].wait(s_c);
+            const int64_t nc = (int64_t)C->row_ptr[r1] - C->row_ptr[r0];
+            if (e == hipSuccess) launch_fill_f64(b.cval, 0.0, nc, s_c);
+            break;
+        }
+        case kStepKernel: {
+            AcBuf &a = acb[sac];
+            BBuf &bq = bb[sb];
+            e = ev_ac_ready[sac].wait(s_c);
+            if (e == hipSuccess) e = ev_b_ready[sb].wait(s_c);
+            if (e != hipSuccess) break;
+            Batch bt;
+            std::memset(&bt, 0, sizeof(bt));
+            bt.nprob = 1;
+            bt.na = a.r1 - a.r0;
+            Prob &q = bt.p0;
+            q.arp = a.arp; q.aci = a.aci; q.aval = a.aval;
+            q.brp = bq.brp; q.bci = bq.bci; q.bval = bq.bval;
+            q.crp = a.crp; q.cci = a.cci; q.cval = a.cval;
+            q.nrows = a.r1 - a.r0;
+            q.ncols = B->ncols;
+            q.krows = bq.r1 - bq.r0;
+            q.a_off = A->row_ptr[a.r0];
+            q.b_off = B->row_ptr[bq.r0];
+            q.c_off = C->row_ptr[a.r0];
+            q.k_lo = bq.r0;
+            q.k_hi = bq.r1;
+            q.accumulate = 1;
+            st = numeric_launch(bt, avg_b, ws, L, s_c);
+            if (st == SPGEMM_OK) e = ev_kdone[ac_outer ? sb : sac].record(s_c);
+            if (e == hipSuccess) e = ev_last_kernel.record(s_c);
+            break;
+        }
+        case kStepD2H: {
+            AcBuf &b = acb[sac];
+            e = ac_outer ? ev_last_kernel.wait(s_d) : ev_kdone[sac].wait(s_d);
+            const int64_t c0 = C->row_ptr[r0], c1 = C->row_ptr[r1];
+            d2h(C->values + c0, b.cval, 8 * (size_t)(c1 - c0));
+            if (e == hipSuccess) e = ev_d2h[sac].record(s_d);
+            if (e == hipSuccess) e = ev_last_d2h.record(s_d);
+            if (e == hipSuccess && ac_outer) e = ev_outer_free.record(s_d);
+            break;
+        }
+        }
+    }
+    hipError_t e2 = hipStreamSynchronize(s_c);
+    hipError_t e3 = hipStreamSynchronize(s_h);
+    hipError_t e4 = hipStreamSynchronize(s_d);
+    cleanup();
+    P->issued_h2d = issued_h;
+    P->issued_d2h = issued_d;
+    if (e != hipSuccess) return hip_fail(e);
+    if (e2 != hipSuccess) return hip_fail(e2);
+    if (e3 != hipSuccess) return hip_fail(e3);
+    if (e4 != hipSuccess) return hip_fail(e4);
+    if (st != SPGEMM_OK) return st;
+    // structure errors flagged by the kernels
+    return read_errors(ws, L, s_c);
+}

@@ -3,14 +3,6 @@
 
 extern "C" {
 
-spgemm_status spgemm_chunked_plan(const spgemm_csr *, const spgemm_csr *, const int32_t *, size_t, int32_t,
-                                  int32_t, spgemm_plan **) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_plan_info_get(const spgemm_plan *, spgemm_plan_info *) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_plan_parts(const spgemm_plan *, int32_t, int32_t *, int32_t) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_plan_steps(const spgemm_plan *, spgemm_plan_step *, int32_t) { return SPGEMM_ERR_UNSUPPORTED; }
-void spgemm_plan_destroy(spgemm_plan *) {}
-spgemm_status spgemm_numeric_chunked(const spgemm_csr *, const spgemm_csr *, spgemm_csr *, spgemm_plan *, void *,
-                                     size_t, hipStream_t, hipStream_t, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
 spgemm_status spgemm_tc_lower(const spgemm_csr *, int32_t *, int32_t *, int32_t *, int64_t *) { return SPGEMM_ERR_UNSUPPORTED; }
 spgemm_status spgemm_tc_workspace_size(const spgemm_csr *, size_t *) { return SPGEMM_ERR_UNSUPPORTED; }
 spgemm_status spgemm_tc(const spgemm_csr *, int64_t *, int64_t *, void *, size_t, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
