@@ -272,3 +272,36 @@ def numeric_chunked(A: HostCsr, B: HostCsr, C: HostCsr, plan: Plan, ws: Optional
                                      plan._h, w.get(nb), nb, st.compute.cuda_stream, st.h2d.cuda_stream,
                                      st.d2h.cuda_stream), "spgemm_numeric_chunked")
     return C
+
+
+# ---------------------------------------------------------------------------
+# triangle counting
+
+def tc_lower(G):
+    """Host preprocessing: (perm, L) with L the strict lower triangle of G after
+    the descending-degree relabelling (ties by ascending id); numpy arrays."""
+    rp = np.ascontiguousarray(G.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(G.col_idx, dtype=np.int32)
+    n = int(G.nrows)
+    h = CsrT(n, n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data if ci.size else None, None)
+    perm = np.empty(max(n, 1), dtype=np.int32)
+    lrp = np.empty(n + 1, dtype=np.int32)
+    lci = np.empty(max(int(rp[-1]) // 2, 1), dtype=np.int32)
+    nnz = ctypes.c_int64(0)
+    check(lib.spgemm_tc_lower(ctypes.byref(h), perm.ctypes.data, lrp.ctypes.data, lci.ctypes.data, ctypes.byref(nnz)),
+          "spgemm_tc_lower")
+    return perm[:n], (n, lrp, lci[:nnz.value].copy())
+
+
+def triangle_count(L: DeviceCsr, ws: Optional[Workspace] = None):
+    """Masked product (L * compressed(L)) o L: per-row int64 counts and the total."""
+    dev = L.row_ptr.device
+    w = _ws(ws, dev)
+    h = L.handle()
+    n = ctypes.c_size_t(0)
+    check(lib.spgemm_tc_workspace_size(ctypes.byref(h), ctypes.byref(n)), "spgemm_tc_workspace_size")
+    counts = torch.empty(max(L.nrows, 1), dtype=torch.int64, device=dev)
+    tot = ctypes.c_int64(0)
+    check(lib.spgemm_tc(ctypes.byref(h), counts.data_ptr(), ctypes.byref(tot), w.get(n.value), n.value,
+                        stream_handle()), "spgemm_tc")
+    return counts[:L.nrows], tot.value

@@ -330,6 +330,13 @@ void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsi
     hipLaunchKernelGGL(k_scatter, dim3(nblk(b.na, kWG)), dim3(kWG), 0, s, b.na, sc);
 }
 
+void launch_scatter(int na, const Sched &sc, hipStream_t s)
+{
+    if (na <= 0) return;
+    ProfScope ps("scatter", s);
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(na, kWG)), dim3(kWG), 0, s, na, sc);
+}
+
 int scan_tiles(int n) { return nblk(n > 0 ? n : 1, kScanTile); }
 
 void launch_scan(const int32_t *val, int n, int64_t *tile_sum, int64_t *prefix, hipStream_t s)

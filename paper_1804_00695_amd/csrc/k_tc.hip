@@ -1,0 +1,252 @@
+// k_tc.hip -- triangle counting as a masked product (Sec. 4.1.2): with L the
+// strict lower triangle of the degree-ordered graph, t_i = sum over k in row i
+// of L of |row k of L intersected with row i of L| = row i of (L*L) o L,
+// summed. Only the pattern is used and no output matrix is formed; the right
+// factor is the compressed L (32 columns per word), so each intersection
+// step is a bitwise AND and a popcount.
+//
+// LDS path: G lanes own row i. The (set, mask) words of compressed row i go
+// into an LDS hash keyed by set; each lane takes entries k of row i and, for
+// every word (s, m) of compressed row k, adds popcount(m & mask_i[s]).
+// Spill path: rows whose own word count exceeds the largest LDS class use a
+// dense bitmap of row i in global memory, one workgroup per row.
+#include <cstdio>
+
+#include "common.h"
+#include "launch.h"
+#include "profile.h"
+
+namespace mls {
+
+constexpr uint32_t kTcEmpty = 0xffffffffu;
+
+__device__ __forceinline__ void tc_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+constexpr int nw_tc(int row_bytes, int rows_per_wave)
+{
+    int per_wave = row_bytes * rows_per_wave;
+    int nw = 65536 / per_wave;
+    return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
+}
+
+template <int G, int CAP>
+__global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int64_t *counts)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_tc(CAP * 8, W);
+    __shared__ uint32_t s_key[NW * W * CAP];
+    __shared__ uint32_t s_msk[NW * W * CAP];
+
+    const int wave = threadIdx.x >> 6;
+    if (wave >= NW) return;
+    const int lw = threadIdx.x & 63;
+    const int slot = lw / G, lane = lw % G;
+    const int rs = wave * W + slot;
+    uint32_t *key = s_key + rs * CAP;
+    uint32_t *msk = s_msk + rs * CAP;
+
+    const Prob P = b.p0;
+    const MLS_G int32_t *__restrict__ lrp = gp(P.arp);
+    const MLS_G int32_t *__restrict__ lci = gp(P.aci);
+    const MLS_G u32x2 *__restrict__ bw = (const MLS_G u32x2 *)P.bw;
+    const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
+    const MLS_G int32_t *perm = gp(sc.perm);
+    const MLS_G int32_t *val = gp(sc.val);
+    const int n_bin = gp(sc.bin_count)[bin];
+    const int start = bin_start(sc.bin_count, bin);
+    const int ntasks = (n_bin + W - 1) / W;
+    TaskIter it = task_iter(ntasks, NW);
+    for (;;) {
+        int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+        if (task < 0) break;
+        const int r = task * W + slot;
+        const bool active = r < n_bin;
+        const int i = active ? perm[start + r] : 0;
+        const int size = active ? val[i] : 0;
+        int logcap = ilog2_ceil(2 * size);
+        if (logcap < 5) logcap = 5;
+        const int cap = 1 << logcap;
+        const uint32_t cmask = (uint32_t)cap - 1u;
+        for (int h = lane; h < cap; h += G) key[h] = kTcEmpty;
+        tc_sync();
+        int ps = 0, pe = 0;
+        if (active) {
+            ps = lrp[i];
+            pe = lrp[i + 1];
+            const MLS_G u32x2 *wi = bw + ps;
+            for (int x = lane; x < size; x += G) {
+                u32x2 wd = wi[x];
+                uint32_t h = hslot(wd.x, logcap);
+                for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                    if (atomicCAS(key + h, kTcEmpty, wd.x) == kTcEmpty) { msk[h] = wd.y; break; }
+                    h = (h + 1u) & cmask;
+                }
+            }
+        }
+        tc_sync();
+        uint32_t cnt = 0;
+        if (active) {
+            for (int p = ps + lane; p < pe; p += G) {
+                const int k = lci[p];
+                const MLS_G u32x2 *wk = bw + lrp[k];
+                const int nk = bwc[k];
+                for (int x = 0; x < nk; ++x) {
+                    u32x2 wd = wk[x];
+                    uint32_t h = hslot(wd.x, logcap);
+                    for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                        uint32_t kk = key[h];
+                        if (kk == wd.x) { cnt += __popc(wd.y & msk[h]); break; }
+                        if (kk == kTcEmpty) break;
+                        h = (h + 1u) & cmask;
+                    }
+                }
+            }
+        }
+        int64_t c = group_sum<G>((int64_t)cnt);
+        if (active && lane == 0) gpw(counts)[i] = c;
+        tc_sync();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_tc_spill(Batch b, Sched sc, int64_t *counts, uint32_t *bitmaps,
+                                                  int64_t words)
+{
+    __shared__ int64_t s_red[kWG / kWave];
+    uint32_t *bm = bitmaps + (int64_t)blockIdx.x * words;
+    const Prob P = b.p0;
+    const MLS_G int32_t *__restrict__ lrp = gp(P.arp);
+    const MLS_G int32_t *__restrict__ lci = gp(P.aci);
+    const MLS_G u32x2 *__restrict__ bw = (const MLS_G u32x2 *)P.bw;
+    const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
+    const int n_bin = gp(sc.bin_count)[kBinSpill];
+    const int start = bin_start(sc.bin_count, kBinSpill);
+    const int nwords = (P.ncols + 31) >> 5;
+    for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
+        const int i = gp(sc.perm)[start + r];
+        for (int w = threadIdx.x; w < nwords; w += kWG)
+            __hip_atomic_store(bm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        __syncthreads();
+        const int ps = lrp[i], pe = lrp[i + 1];
+        const int ni = bwc[i];
+        for (int x = threadIdx.x; x < ni; x += kWG) {
+            u32x2 wd = bw[ps + x];
+            __hip_atomic_store(bm + wd.x, wd.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        __syncthreads();
+        int64_t cnt = 0;
+        for (int p = ps + threadIdx.x; p < pe; p += kWG) {
+            const int k = lci[p];
+            const MLS_G u32x2 *wk = bw + lrp[k];
+            const int nk = bwc[k];
+            for (int x = 0; x < nk; ++x) {
+                u32x2 wd = wk[x];
+                cnt += __popc(wd.y & __hip_atomic_load(bm + wd.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+        }
+        cnt = group_sum<kWave>(cnt);
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t s = 0;
+            for (int w = 0; w < kWG / kWave; ++w) s += s_red[w];
+            gpw(counts)[i] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// Bins of L's rows by the word count of row i itself (the size of its hash
+// table); rows without entries count zero triangles.
+__global__ void k_tc_bin(Batch b, Sched sc, int force_spill)
+{
+    __shared__ int cnt[kNumBins];
+    if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < b.na) {
+        const Prob P = b.p0;
+        int len = gp(P.arp)[i + 1] - gp(P.arp)[i];
+        int size = gp(P.bwc)[i];
+        int c;
+        if (len == 0) c = kBinEmpty;
+        else if (force_spill) c = kBinSpill;
+        else c = size <= kFillCap[0] / 2 ? 0 : (size <= kFillCap[1] / 2 ? 1 : (size <= kFillCap[2] / 2 ? 2 : kBinSpill));
+        gpw(sc.val)[i] = size;
+        gpw(sc.cls)[i] = (uint8_t)c;
+        atomicAdd(&cnt[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(sc.bin_count + threadIdx.x, cnt[threadIdx.x]);
+}
+
+__global__ void k_sum_i64(const int64_t *x, int n, unsigned long long *total)
+{
+    __shared__ int64_t s_red[kWG / kWave];
+    int64_t s = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) s += gp(x)[i];
+    s = group_sum<kWave>(s);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kWG / kWave; ++w) t += s_red[w];
+        if (t) atomicAdd(total, (unsigned long long)t);
+    }
+}
+
+template <typename K>
+static int tc_grid(K kernel, int threads)
+{
+    static int cus = device_cu_count();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+template <int G, int CAP>
+static void launch_tc_class(const Batch &b, const Sched &sc, int bin, int64_t *counts, hipStream_t s)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_tc(CAP * 8, W);
+    static int grid = tc_grid(k_tc_lds<G, CAP>, NW * kWave);
+    static char name[64];
+    if (!name[0]) snprintf(name, sizeof(name), "tc_lds_G%d_C%d", G, CAP);
+    ProfScope ps(name, s);
+    hipLaunchKernelGGL((k_tc_lds<G, CAP>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, counts);
+}
+
+void launch_tc_bin(const Batch &b, const Sched &sc, int force_spill, hipStream_t s)
+{
+    if (b.na <= 0) return;
+    int grid = (b.na + kWG - 1) / kWG;
+    {
+        ProfScope ps("tc_bin", s);
+        hipLaunchKernelGGL(k_tc_bin, dim3(grid), dim3(kWG), 0, s, b, sc, force_spill);
+    }
+    launch_scatter(b.na, sc, s);
+}
+
+void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long long *total, uint32_t *spill_bitmaps,
+               int spill_slots, int64_t spill_words, hipStream_t s)
+{
+    if (b.na <= 0) return;
+    launch_tc_class<16, kFillCap[0]>(b, sc, 0, counts, s);
+    launch_tc_class<64, kFillCap[1]>(b, sc, 1, counts, s);
+    launch_tc_class<64, kFillCap[2]>(b, sc, 2, counts, s);
+    {
+        ProfScope ps("tc_spill", s);
+        hipLaunchKernelGGL(k_tc_spill, dim3(spill_slots), dim3(kWG), 0, s, b, sc, counts, spill_bitmaps, spill_words);
+    }
+    ProfScope ps("tc_sum", s);
+    hipLaunchKernelGGL(k_sum_i64, dim3(1024), dim3(kWG), 0, s, counts, b.na, total);
+}
+
+}  // namespace mls

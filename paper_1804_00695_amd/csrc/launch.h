@@ -32,7 +32,8 @@ void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s);
 // Triangle counting over the binned rows of L (A = B = L in the batch).
 void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long long *total,
                uint32_t *spill_bitmaps, int spill_slots, int64_t spill_words, hipStream_t s);
-void launch_tc_bin(const Batch &b, const Sched &sc, hipStream_t s);
+void launch_tc_bin(const Batch &b, const Sched &sc, int force_spill, hipStream_t s);
+void launch_scatter(int na, const Sched &sc, hipStream_t s);
 
 // Backward (adjoint) over the binned rows of W (= pattern of C).
 void launch_backward(const Batch &b, const Sched &sc, const double *wval, double *dA, double *dB, int G,

@@ -3,9 +3,6 @@
 
 extern "C" {
 
-spgemm_status spgemm_tc_lower(const spgemm_csr *, int32_t *, int32_t *, int32_t *, int64_t *) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_tc_workspace_size(const spgemm_csr *, size_t *) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_tc(const spgemm_csr *, int64_t *, int64_t *, void *, size_t, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
 spgemm_status spgemm_batch_plan_create(int32_t, const spgemm_csr *, const spgemm_csr *, spgemm_csr *, int32_t, int32_t,
                                        void *, size_t, hipStream_t, spgemm_batch_plan **) { return SPGEMM_ERR_UNSUPPORTED; }
 spgemm_status spgemm_batch_plan_run(spgemm_batch_plan *, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
