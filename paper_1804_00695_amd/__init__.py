@@ -305,3 +305,83 @@ def triangle_count(L: DeviceCsr, ws: Optional[Workspace] = None):
     check(lib.spgemm_tc(ctypes.byref(h), counts.data_ptr(), ctypes.byref(tot), w.get(n.value), n.value,
                         stream_handle()), "spgemm_tc")
     return counts[:L.nrows], tot.value
+
+
+# ---------------------------------------------------------------------------
+# adjoint (backward) and its unfused per-call counterpart
+
+def backward(A: DeviceCsr, B: DeviceCsr, W: DeviceCsr, need_a: bool = True, need_b: bool = True,
+             ws: Optional[Workspace] = None):
+    """Fused adjoint of sum(W o (A*B)): (dA values on pat(A), dB values on pat(B))."""
+    dev = A.row_ptr.device
+    w = _ws(ws, dev)
+    n = ctypes.c_size_t(0)
+    ha, hb, hw = A.handle(), B.handle(), W.handle()
+    check(lib.spgemm_backward_workspace_size(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(hw), ctypes.byref(n)),
+          "spgemm_backward_workspace_size")
+    dA = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=dev) if need_a else None
+    dB = torch.empty(max(B.nnz, 1), dtype=torch.float64, device=dev) if need_b else None
+    check(lib.spgemm_backward(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(hw), _ptr(dA), _ptr(dB),
+                              w.get(n.value), n.value, stream_handle()), "spgemm_backward")
+    return (None if dA is None else dA[:A.nnz]), (None if dB is None else dB[:B.nnz])
+
+
+def transpose(M: DeviceCsr, ws: Optional[Workspace] = None) -> DeviceCsr:
+    dev = M.row_ptr.device
+    w = _ws(ws, dev)
+    n = ctypes.c_size_t(0)
+    hm = M.handle()
+    check(lib.spgemm_transpose_workspace_size(ctypes.byref(hm), ctypes.byref(n)), "spgemm_transpose_workspace_size")
+    T = DeviceCsr(M.ncols, M.nrows, torch.empty(M.ncols + 1, dtype=torch.int32, device=dev),
+                  torch.empty(M.nnz, dtype=torch.int32, device=dev),
+                  None if M.values is None else torch.empty(M.nnz, dtype=torch.float64, device=dev))
+    check(lib.spgemm_transpose(ctypes.byref(hm), ctypes.byref(T.handle()), w.get(n.value), n.value, stream_handle()),
+          "spgemm_transpose")
+    return T
+
+
+def mask_gather(X: DeviceCsr, P: DeviceCsr) -> torch.Tensor:
+    """Values of X at the entries of pattern P (0 where X has none)."""
+    out = torch.empty(max(P.nnz, 1), dtype=torch.float64, device=X.row_ptr.device)
+    check(lib.spgemm_mask_gather(ctypes.byref(X.handle()), ctypes.byref(P.handle()), out.data_ptr(), stream_handle()),
+          "spgemm_mask_gather")
+    return out[:P.nnz]
+
+
+def backward_unfused(A: DeviceCsr, B: DeviceCsr, W: DeviceCsr, ws: Optional[Workspace] = None):
+    """The plain per-call adjoint: dA = (W B^T) o pat(A), dB = (A^T W) o pat(B),
+    each through a transpose, a full two-phase product and a masked gather."""
+    Bt = transpose(B, ws)
+    dA = mask_gather(spgemm(W, Bt, ws), A)
+    At = transpose(A, ws)
+    dB = mask_gather(spgemm(At, W, ws), B)
+    return dA, dB
+
+
+class SpGEMMFn(torch.autograd.Function):
+    """c_values = values of A*B on a fixed structure; differentiable in the
+    values of A and B (structures are constants)."""
+
+    @staticmethod
+    def forward(ctx, a_values, b_values, A, B, C):
+        A2 = DeviceCsr(A.nrows, A.ncols, A.row_ptr, A.col_idx, a_values.detach().contiguous())
+        B2 = DeviceCsr(B.nrows, B.ncols, B.row_ptr, B.col_idx, b_values.detach().contiguous())
+        C2 = DeviceCsr(C.nrows, C.ncols, C.row_ptr, C.col_idx,
+                       torch.empty(C.nnz, dtype=torch.float64, device=a_values.device))
+        numeric(A2, B2, C2)
+        ctx.A, ctx.B, ctx.C = A2, B2, C2
+        return C2.values
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        W = DeviceCsr(ctx.C.nrows, ctx.C.ncols, ctx.C.row_ptr, ctx.C.col_idx, grad_c.contiguous())
+        dA, dB = backward(ctx.A, ctx.B, W, need_a=ctx.needs_input_grad[0], need_b=ctx.needs_input_grad[1])
+        return dA, dB, None, None, None
+
+
+def spgemm_autograd(A: DeviceCsr, a_values: torch.Tensor, B: DeviceCsr, b_values: torch.Tensor):
+    """Differentiable C = A*B: returns (C structure as DeviceCsr, c_values with grad_fn)."""
+    C = symbolic(DeviceCsr(A.nrows, A.ncols, A.row_ptr, A.col_idx, None),
+                 DeviceCsr(B.nrows, B.ncols, B.row_ptr, B.col_idx, None), with_values=False)
+    cv = SpGEMMFn.apply(a_values, b_values, A, B, C)
+    return C, cv

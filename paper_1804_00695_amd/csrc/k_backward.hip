@@ -1,0 +1,330 @@
+// k_backward.hip -- adjoint of loss(A, B) = sum_ij W_ij (A*B)_ij with W given
+// on the pattern of C = A*B (the product's reverse mode; not in the paper):
+//   dA_ik = sum_{j in B_k} W_ij b_kj      (only on the pattern of A)
+//   dB_kj = sum_{i : k in A_i} a_ik W_ij  (only on the pattern of B)
+// Fused, with no dense or product-sized intermediate: G lanes own row i;
+// W_i goes into an LDS hash (column -> W value); for every entry (i, k) the
+// lanes take distinct entries of B_k, look up W_ij, accumulate W_ij b_kj for
+// dA (group reduction) and add a_ik W_ij into dB with a device fp64 atomic.
+// Rows of W too long for LDS take a workgroup-per-row path that binary-
+// searches W_i in global memory.
+//
+// Also here: CSR transpose (count, scan, scatter, per-row sort) and a masked
+// gather out[e] = X(row(e), col(e)) over a pattern, used by the unfused
+// per-call adjoint (W B^T masked to pat(A), A^T W masked to pat(B)).
+#include <cstdio>
+
+#include "common.h"
+#include "launch.h"
+#include "profile.h"
+
+namespace mls {
+
+constexpr int kBwdUnroll = 4;
+
+__device__ __forceinline__ void bwd_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+constexpr int nw_bwd(int row_bytes, int rows_per_wave)
+{
+    int per_wave = row_bytes * rows_per_wave;
+    int nw = 65536 / per_wave;
+    return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
+}
+
+__device__ __forceinline__ bool w_lookup(const int *key, const double *wv, int logcap, int j, double &w)
+{
+    const uint32_t cmask = (1u << logcap) - 1u;
+    uint32_t h = hslot((uint32_t)j, logcap);
+    for (uint32_t probe = 0; probe <= cmask; ++probe) {
+        int k = key[h];
+        if (k == j) { w = wv[h]; return true; }
+        if (k == -1) return false;
+        h = (h + 1u) & cmask;
+    }
+    return false;
+}
+
+template <int G, int CAP>
+__global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, double *dA, double *dB)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_bwd(CAP * 12, W);
+    __shared__ int s_key[NW * W * CAP];
+    __shared__ double s_wv[NW * W * CAP];
+
+    const int wave = threadIdx.x >> 6;
+    if (wave >= NW) return;
+    const int lw = threadIdx.x & 63;
+    const int slot = lw / G, lane = lw % G;
+    const int rs = wave * W + slot;
+    int *key = s_key + rs * CAP;
+    double *wv = s_wv + rs * CAP;
+
+    const Prob P = b.p0;
+    const MLS_G int32_t *__restrict__ arp = gp(P.arp);
+    const MLS_G int32_t *__restrict__ aci = gp(P.aci);
+    const MLS_G double *__restrict__ aval = gp(P.aval);
+    const MLS_G int32_t *__restrict__ brp = gp(P.brp);
+    const MLS_G int32_t *__restrict__ bci = gp(P.bci);
+    const MLS_G double *__restrict__ bval = gp(P.bval);
+    const MLS_G int32_t *__restrict__ wrp = gp(P.crp);
+    const MLS_G int32_t *__restrict__ wci = gp(P.cci);
+    const MLS_G double *__restrict__ wval = gp(P.cval);
+    MLS_G double *__restrict__ gdA = gpw(dA);
+    const MLS_G int32_t *perm = gp(sc.perm);
+    const MLS_G int32_t *val = gp(sc.val);
+    const int n_bin = gp(sc.bin_count)[bin];
+    const int start = bin_start(sc.bin_count, bin);
+    const int ntasks = (n_bin + W - 1) / W;
+    TaskIter it = task_iter(ntasks, NW);
+    for (;;) {
+        int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+        if (task < 0) break;
+        const int r = task * W + slot;
+        const bool active = r < n_bin;
+        const int i = active ? perm[start + r] : 0;
+        const int nw = active ? val[i] : 0;
+        int logcap = ilog2_ceil(2 * nw);
+        if (logcap < 5) logcap = 5;
+        const int cap = 1 << logcap;
+        const uint32_t cmask = (uint32_t)cap - 1u;
+        for (int h = lane; h < cap; h += G) key[h] = -1;
+        bwd_sync();
+        int ps = 0, pe = 0;
+        if (active) {
+            const int ws0 = wrp[i];
+            for (int e = lane; e < nw; e += G) {
+                int j = wci[ws0 + e];
+                uint32_t h = hslot((uint32_t)j, logcap);
+                for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                    if (atomicCAS(key + h, -1, j) == -1) { wv[h] = wval[ws0 + e]; break; }
+                    h = (h + 1u) & cmask;
+                }
+            }
+            ps = arp[i];
+            pe = arp[i + 1];
+        }
+        bwd_sync();
+        bool bad = false;
+        // loop bounds are made uniform across the wave so that the group
+        // reductions (cross-lane shuffles) run with every lane present
+        int pmax = pe - ps;
+        for (int o = 32; o >= 1; o >>= 1) pmax = max(pmax, __shfl_xor(pmax, o, kWave));
+        for (int off = 0; off < pmax; off += kBwdUnroll) {
+            double av[kBwdUnroll], part[kBwdUnroll];
+            int q0[kBwdUnroll], q1[kBwdUnroll];
+#pragma unroll
+            for (int u = 0; u < kBwdUnroll; ++u) {
+                const int p = ps + off + u;
+                q0[u] = 0; q1[u] = 0; av[u] = 0.0; part[u] = 0.0;
+                if (active && p < pe) {
+                    int k = aci[p];
+                    av[u] = aval[p];
+                    q0[u] = brp[k];
+                    q1[u] = brp[k + 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBwdUnroll; ++u) {
+                for (int q = q0[u] + lane; q < q1[u]; q += G) {
+                    double w;
+                    if (!w_lookup(key, wv, logcap, bci[q], w)) { bad = true; continue; }
+                    part[u] += w * bval[q];
+                    if (dB) atomicAdd(dB + q, av[u] * w);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBwdUnroll; ++u) {
+                double s = group_sum<G>(part[u]);
+                const int p = ps + off + u;
+                if (dA && active && lane == 0 && p < pe) gdA[p] = s;
+            }
+        }
+        if (bad) atomicOr(sc.err, kErrStructure);
+        bwd_sync();
+    }
+}
+
+__device__ __forceinline__ int bsearch_w(const MLS_G int32_t *cols, int n, int j)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cols[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && cols[lo] == j) ? lo : -1;
+}
+
+// Rows with long W_i: one workgroup per row, W_i searched in global memory;
+// dA is accumulated with atomics (dA was zeroed).
+__global__ __launch_bounds__(kWG) void k_bwd_spill(Batch b, Sched sc, double *dA, double *dB)
+{
+    const Prob P = b.p0;
+    const MLS_G int32_t *__restrict__ aci = gp(P.aci);
+    const MLS_G double *__restrict__ aval = gp(P.aval);
+    const MLS_G int32_t *__restrict__ brp = gp(P.brp);
+    const MLS_G int32_t *__restrict__ bci = gp(P.bci);
+    const MLS_G double *__restrict__ bval = gp(P.bval);
+    const int n_bin = gp(sc.bin_count)[kBinSpill];
+    const int start = bin_start(sc.bin_count, kBinSpill);
+    for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
+        const int i = gp(sc.perm)[start + r];
+        const int w0 = gp(P.crp)[i], nw = gp(P.crp)[i + 1] - w0;
+        const MLS_G int32_t *wc = gp(P.cci) + w0;
+        const MLS_G double *wvv = gp(P.cval) + w0;
+        bool bad = false;
+        for (int p = gp(P.arp)[i]; p < gp(P.arp)[i + 1]; ++p) {
+            const int k = aci[p];
+            const double a = aval[p];
+            double part = 0.0;
+            for (int q = brp[k] + threadIdx.x; q < brp[k + 1]; q += kWG) {
+                int pos = bsearch_w(wc, nw, bci[q]);
+                if (pos < 0) { bad = true; continue; }
+                const double w = wvv[pos];
+                part += w * bval[q];
+                if (dB) atomicAdd(dB + q, a * w);
+            }
+            if (dA && part != 0.0) atomicAdd(dA + p, part);
+        }
+        if (bad) atomicOr(sc.err, kErrStructure);
+    }
+}
+
+template <typename K>
+static int bwd_grid(K kernel, int threads)
+{
+    static int cus = device_cu_count();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+template <int G, int CAP>
+static void launch_bwd_class(const Batch &b, const Sched &sc, int bin, double *dA, double *dB, hipStream_t s)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_bwd(CAP * 12, W);
+    static int grid = bwd_grid(k_bwd_lds<G, CAP>, NW * kWave);
+    static char name[64];
+    if (!name[0]) snprintf(name, sizeof(name), "bwd_lds_G%d_C%d", G, CAP);
+    ProfScope ps(name, s);
+    hipLaunchKernelGGL((k_bwd_lds<G, CAP>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, dA, dB);
+}
+
+void launch_backward(const Batch &b, const Sched &sc, const double *wval, double *dA, double *dB, int G,
+                     hipStream_t s)
+{
+    (void)wval;
+    if (b.na <= 0) return;
+    switch (G) {
+    case 8: launch_bwd_class<8, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
+    case 16: launch_bwd_class<16, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
+    case 64: launch_bwd_class<64, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
+    default: launch_bwd_class<32, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
+    }
+    if (G >= 64) launch_bwd_class<64, kFillCap[1]>(b, sc, 1, dA, dB, s);
+    else launch_bwd_class<32, kFillCap[1]>(b, sc, 1, dA, dB, s);
+    launch_bwd_class<64, kFillCap[2]>(b, sc, 2, dA, dB, s);
+    static int spill_grid = device_cu_count();
+    ProfScope ps("bwd_spill", s);
+    hipLaunchKernelGGL(k_bwd_spill, dim3(spill_grid), dim3(kWG), 0, s, b, sc, dA, dB);
+}
+
+// ---------------------------------------------------------------------------
+// transpose
+
+__global__ void k_tr_count(int32_t nrows, const int32_t *rp, const int32_t *ci, int32_t *cnt)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    for (int p = gp(rp)[i]; p < gp(rp)[i + 1]; ++p) atomicAdd(cnt + gp(ci)[p], 1);
+}
+
+__global__ void k_tr_rowptr(int32_t n, const int64_t *prefix, int32_t *trp)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) gpw(trp)[i] = (int32_t)gp(prefix)[i];
+}
+
+__global__ void k_tr_scatter(int32_t nrows, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *trp,
+                             int32_t *cursor, int32_t *tci, double *tv)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    for (int p = gp(rp)[i]; p < gp(rp)[i + 1]; ++p) {
+        int c = gp(ci)[p];
+        int pos = gp(trp)[c] + atomicAdd(cursor + c, 1);
+        gpw(tci)[pos] = i;
+        if (v) gpw(tv)[pos] = gp(v)[p];
+    }
+}
+
+// per-row insertion sort of (column, value) pairs (rows of a transpose are
+// short for the workloads here; long rows still sort correctly, just slowly)
+__global__ void k_tr_sort(int32_t n, const int32_t *trp, int32_t *tci, double *tv)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int s = gp(trp)[r], e = gp(trp)[r + 1];
+    MLS_G int32_t *c = gpw(tci);
+    MLS_G double *v = gpw(tv);
+    for (int a = s + 1; a < e; ++a) {
+        int key = c[a];
+        double kv = tv ? v[a] : 0.0;
+        int b2 = a - 1;
+        while (b2 >= s && c[b2] > key) {
+            c[b2 + 1] = c[b2];
+            if (tv) v[b2 + 1] = v[b2];
+            --b2;
+        }
+        c[b2 + 1] = key;
+        if (tv) v[b2 + 1] = kv;
+    }
+}
+
+void launch_transpose(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *ci, const double *v,
+                      int32_t *trp, int32_t *tci, double *tv, int32_t *cursor, int64_t *tile_sum, int64_t *prefix,
+                      int32_t *cnt, hipStream_t s)
+{
+    ProfScope ps("transpose", s);
+    launch_fill_i32(cnt, 0, ncols, s);
+    launch_fill_i32(cursor, 0, ncols, s);
+    if (nrows > 0)
+        hipLaunchKernelGGL(k_tr_count, dim3((nrows + kWG - 1) / kWG), dim3(kWG), 0, s, nrows, rp, ci, cnt);
+    launch_scan(cnt, ncols, tile_sum, prefix, s);
+    hipLaunchKernelGGL(k_tr_rowptr, dim3((ncols + kWG) / kWG), dim3(kWG), 0, s, ncols, prefix, trp);
+    if (nrows > 0)
+        hipLaunchKernelGGL(k_tr_scatter, dim3((nrows + kWG - 1) / kWG), dim3(kWG), 0, s, nrows, rp, ci, v, trp, cursor,
+                           tci, tv);
+    if (ncols > 0) hipLaunchKernelGGL(k_tr_sort, dim3((ncols + kWG - 1) / kWG), dim3(kWG), 0, s, ncols, trp, tci, tv);
+}
+
+// out[e] = X(r, c) for the e-th entry (r, c) of pattern P, else 0.0
+__global__ void k_mask_gather(int32_t nrows, const int32_t *xrp, const int32_t *xci, const double *xv,
+                              const int32_t *prp, const int32_t *pci, double *out)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const int xs = gp(xrp)[r], xn = gp(xrp)[r + 1] - xs;
+    for (int p = gp(prp)[r]; p < gp(prp)[r + 1]; ++p) {
+        int pos = bsearch_w(gp(xci) + xs, xn, gp(pci)[p]);
+        gpw(out)[p] = pos >= 0 ? gp(xv)[xs + pos] : 0.0;
+    }
+}
+
+void launch_mask_gather(int32_t nrows, const int32_t *xrp, const int32_t *xci, const double *xv, const int32_t *prp,
+                        const int32_t *pci, double *out, hipStream_t s)
+{
+    if (nrows <= 0) return;
+    ProfScope ps("mask_gather", s);
+    hipLaunchKernelGGL(k_mask_gather, dim3((nrows + kWG - 1) / kWG), dim3(kWG), 0, s, nrows, xrp, xci, xv, prp, pci,
+                       out);
+}
+
+}  // namespace mls

@@ -7,11 +7,5 @@ spgemm_status spgemm_batch_plan_create(int32_t, const spgemm_csr *, const spgemm
                                        void *, size_t, hipStream_t, spgemm_batch_plan **) { return SPGEMM_ERR_UNSUPPORTED; }
 spgemm_status spgemm_batch_plan_run(spgemm_batch_plan *, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
 void spgemm_batch_plan_destroy(spgemm_batch_plan *) {}
-spgemm_status spgemm_backward_workspace_size(const spgemm_csr *, const spgemm_csr *, const spgemm_csr *, size_t *) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_backward(const spgemm_csr *, const spgemm_csr *, const spgemm_csr *, double *, double *, void *,
-                              size_t, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_transpose_workspace_size(const spgemm_csr *, size_t *) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_transpose(const spgemm_csr *, spgemm_csr *, void *, size_t, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
-spgemm_status spgemm_mask_gather(const spgemm_csr *, const spgemm_csr *, double *, hipStream_t) { return SPGEMM_ERR_UNSUPPORTED; }
 
 }

@@ -1,0 +1,102 @@
+"""GPU parity of the adjoint of loss = sum(W o (A*B)): fused kernels vs the
+oracle's gradient (|g - g_ref| <= 1e-10 * the oracle's |.| sum), vs the
+unfused per-call path, vs directional finite differences through the GPU
+forward (exact up to rounding: the loss is linear in each factor), and
+torch.autograd.gradcheck on a tiny instance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+mls = pytest.importorskip("paper_1804_00695_amd")
+TOL = 1e-10
+
+
+def instance(m, k, n, la, lb, seeds):
+    A = synth.poisson_csr(m, k, la, seeds[0])
+    B = synth.poisson_csr(k, n, lb, seeds[1])
+    C, _ = oracle.spgemm(A, B, with_abs=False)
+    W = synth.Csr(C.nrows, C.ncols, C.row_ptr, C.col_idx, synth.normal_values(C.nnz, seeds[2]))
+    return A, B, W
+
+
+@pytest.mark.parametrize("shape", [(2000, 2000, 2000, 8.0, 8.0), (500, 3000, 700, 20.0, 3.0), (64, 64, 64, 30.0, 30.0)])
+def test_fused_vs_oracle(shape):
+    A, B, W = instance(*shape, seeds=(8, 9, 10))
+    dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W))
+    torch.cuda.synchronize()
+    rA, rB, aA, aB = oracle.backward(A, B, W)
+    assert np.all(np.abs(dA.cpu().numpy() - rA) <= TOL * aA + 1e-300)
+    assert np.all(np.abs(dB.cpu().numpy() - rB) <= TOL * aB + 1e-300)
+
+
+def test_long_w_rows_spill():
+    g = synth.rng(3)
+    m, k, n = 40, 3000, 20000
+    rows = [np.sort(g.choice(k, 300, replace=False)) for _ in range(m)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    A = synth.Csr(m, k, rp, np.concatenate(rows).astype(np.int32), g.standard_normal(int(rp[-1])))
+    B = synth.poisson_csr(k, n, 12.0, 4)
+    C, _ = oracle.spgemm(A, B, with_abs=False)
+    assert np.diff(C.row_ptr).max() > 2048
+    W = synth.Csr(C.nrows, C.ncols, C.row_ptr, C.col_idx, synth.normal_values(C.nnz, 5))
+    dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W))
+    rA, rB, aA, aB = oracle.backward(A, B, W)
+    assert np.all(np.abs(dA.cpu().numpy() - rA) <= TOL * aA + 1e-300)
+    assert np.all(np.abs(dB.cpu().numpy() - rB) <= TOL * aB + 1e-300)
+
+
+def test_unfused_matches_fused():
+    A, B, W = instance(1500, 1200, 1300, 6.0, 7.0, seeds=(11, 12, 13))
+    dA_, dB_, dW = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W)
+    fa, fb = mls.backward(dA_, dB_, dW)
+    ua, ub = mls.backward_unfused(dA_, dB_, dW)
+    rA, rB, aA, aB = oracle.backward(A, B, W)
+    assert np.all(np.abs(ua.cpu().numpy() - rA) <= TOL * aA + 1e-300)
+    assert np.all(np.abs(ub.cpu().numpy() - rB) <= TOL * aB + 1e-300)
+
+
+def test_transpose_exact():
+    M = synth.poisson_csr(700, 900, 9.0, 21)
+    T = mls.transpose(mls.DeviceCsr.from_host(M))
+    rp, ci, v = T.numpy()
+    ref = synth.transpose(M)
+    assert np.array_equal(rp, ref.row_ptr) and np.array_equal(ci, ref.col_idx) and np.array_equal(v, ref.values)
+
+
+def test_directional_finite_differences():
+    A, B, W = instance(2000, 2000, 2000, 8.0, 8.0, seeds=(8, 9, 10))
+    dA_, dB_, dW = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W)
+    C = mls.symbolic(dA_, dB_)
+    gA, gB = mls.backward(dA_, dB_, dW)
+    g = synth.rng(50)
+
+    def loss(av, bv):
+        a2 = mls.DeviceCsr(A.nrows, A.ncols, dA_.row_ptr, dA_.col_idx, av)
+        b2 = mls.DeviceCsr(B.nrows, B.ncols, dB_.row_ptr, dB_.col_idx, bv)
+        mls.numeric(a2, b2, C)
+        return float(torch.dot(C.values, dW.values))
+
+    for _ in range(3):
+        V = torch.from_numpy(g.standard_normal(A.nnz)).cuda()
+        fd = (loss(dA_.values + V, dB_.values) - loss(dA_.values - V, dB_.values)) / 2.0
+        ref = float(torch.dot(gA, V))
+        assert abs(fd - ref) <= 1e-9 * max(1.0, abs(ref))
+        V = torch.from_numpy(g.standard_normal(B.nnz)).cuda()
+        fd = (loss(dA_.values, dB_.values + V) - loss(dA_.values, dB_.values - V)) / 2.0
+        ref = float(torch.dot(gB, V))
+        assert abs(fd - ref) <= 1e-9 * max(1.0, abs(ref))
+
+
+def test_autograd_gradcheck_tiny():
+    A = synth.random_csr(6, 5, 0.5, 1)
+    B = synth.random_csr(5, 7, 0.5, 2)
+    dA_, dB_ = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B)
+    av = dA_.values.clone().requires_grad_(True)
+    bv = dB_.values.clone().requires_grad_(True)
+    C = mls.symbolic(dA_, dB_, with_values=False)
+    f = lambda a, b: mls.SpGEMMFn.apply(a, b, dA_, dB_, C)
+    assert torch.autograd.gradcheck(f, (av, bv), eps=1e-6, atol=1e-8)
