@@ -272,6 +272,9 @@ spgemm_status spgemm_batch_plan_create(int32_t nbatch, const spgemm_csr *A, cons
                                        spgemm_csr *C, int32_t group_size, int32_t use_graph, void *ws,
                                        size_t ws_bytes, hipStream_t stream, spgemm_batch_plan **out);
 spgemm_status spgemm_batch_plan_run(spgemm_batch_plan *plan, hipStream_t stream);
+/* Lanes per row the plan uses for its first LDS class (the autotuned value
+ * when created with group_size 0). */
+int32_t spgemm_batch_plan_group_size(const spgemm_batch_plan *plan);
 void spgemm_batch_plan_destroy(spgemm_batch_plan *plan);
 
 /* ------------------------------------------------------------------------

@@ -385,3 +385,83 @@ def spgemm_autograd(A: DeviceCsr, a_values: torch.Tensor, B: DeviceCsr, b_values
                  DeviceCsr(B.nrows, B.ncols, B.row_ptr, B.col_idx, None), with_values=False)
     cv = SpGEMMFn.apply(a_values, b_values, A, B, C)
     return C, cv
+
+
+# ---------------------------------------------------------------------------
+# batches of independent products
+
+def _handles(mats):
+    arr = (CsrT * len(mats))()
+    for i, m in enumerate(mats):
+        arr[i] = m.handle()
+    return arr
+
+
+def batch_workspace_size(As, Bs) -> int:
+    n = ctypes.c_size_t(0)
+    check(lib.spgemm_batch_workspace_size(len(As), _handles(As), _handles(Bs), ctypes.byref(n)),
+          "spgemm_batch_workspace_size")
+    return n.value
+
+
+def batch_symbolic(As, Bs, ws: Optional[Workspace] = None, with_values: bool = True):
+    """Structures of all C_t = A_t * B_t: one count pass (one readback), one fill pass."""
+    dev = As[0].row_ptr.device
+    w = _ws(ws, dev)
+    nb = batch_workspace_size(As, Bs)
+    p = w.get(nb)
+    Cs = [DeviceCsr(a.nrows, b.ncols, torch.empty(a.nrows + 1, dtype=torch.int32, device=dev),
+                    torch.empty(0, dtype=torch.int32, device=dev), None) for a, b in zip(As, Bs)]
+    nnz = (ctypes.c_int64 * len(As))()
+    ha, hb = _handles(As), _handles(Bs)
+    check(lib.spgemm_batch_symbolic(len(As), ha, hb, _handles(Cs), 0, nnz, p, nb, stream_handle()),
+          "spgemm_batch_symbolic(count)")
+    for c, z in zip(Cs, nnz):
+        c.col_idx = torch.empty(int(z), dtype=torch.int32, device=dev)
+        if with_values:
+            c.values = torch.empty(int(z), dtype=torch.float64, device=dev)
+    hc = _handles(Cs)
+    for i, c in enumerate(Cs):   # handles must carry col_idx even when nnz == 0
+        if c.nnz == 0:
+            hc[i].col_idx = c.row_ptr.data_ptr()
+    check(lib.spgemm_batch_symbolic(len(As), ha, hb, hc, 1, None, p, nb, stream_handle()),
+          "spgemm_batch_symbolic(fill)")
+    return Cs
+
+
+def batch_numeric(As, Bs, Cs, ws: Optional[Workspace] = None):
+    dev = As[0].row_ptr.device
+    w = _ws(ws, dev)
+    nb = batch_workspace_size(As, Bs)
+    check(lib.spgemm_batch_numeric(len(As), _handles(As), _handles(Bs), _handles(Cs), w.get(nb), nb,
+                                   stream_handle()), "spgemm_batch_numeric")
+    return Cs
+
+
+class BatchPlan:
+    """Reusable numeric plan over a batch with fixed structure (HIP graph replay).
+
+    Owns its own workspace: the binning lives there between runs."""
+
+    def __init__(self, As, Bs, Cs, group_size: int = 0, use_graph: bool = True):
+        dev = As[0].row_ptr.device
+        self.ws = Workspace(dev)
+        nb = batch_workspace_size(As, Bs)
+        self._keep = (As, Bs, Cs, _handles(As), _handles(Bs), _handles(Cs))
+        out = ctypes.c_void_p(0)
+        check(lib.spgemm_batch_plan_create(len(As), self._keep[3], self._keep[4], self._keep[5], group_size,
+                                           1 if use_graph else 0, self.ws.get(nb), nb, stream_handle(),
+                                           ctypes.byref(out)), "spgemm_batch_plan_create")
+        self._h = out.value
+
+    @property
+    def group_size(self) -> int:
+        return lib.spgemm_batch_plan_group_size(self._h)
+
+    def run(self):
+        check(lib.spgemm_batch_plan_run(self._h, stream_handle()), "spgemm_batch_plan_run")
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib.spgemm_batch_plan_destroy(self._h)
+            self._h = None

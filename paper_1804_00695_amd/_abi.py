@@ -68,6 +68,7 @@ SIGNATURES = {
     "spgemm_batch_plan_create": (ctypes.c_int, [c_int32, CSRP, CSRP, CSRP, c_int32, c_int32, P, c_size_t, P,
                                                 ctypes.POINTER(P)]),
     "spgemm_batch_plan_run": (ctypes.c_int, [P, P]),
+    "spgemm_batch_plan_group_size": (c_int32, [P]),
     "spgemm_batch_plan_destroy": (None, [P]),
     "spgemm_backward_workspace_size": (ctypes.c_int, [CSRP, CSRP, CSRP, SZP]),
     "spgemm_backward": (ctypes.c_int, [CSRP, CSRP, CSRP, P, P, P, c_size_t, P]),
