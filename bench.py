@@ -1,19 +1,32 @@
 """Benchmark of the two-phase SpGEMM hot path on one MI355X.
 
-Workload (the headline configuration): C = A*A with A the 27-point stencil on
-a 128^3 grid (2,097,152 rows, 55,742,968 entries), fp64 values: diagonal 26,
-off-diagonals -(1 + U(-0.1, 0.1)) (seed 2), int32 CSR indices. One step is
-one pass of the whole plain path in HBM: symbolic count (row binning, column
-compression, LDS hash union, scan, nnz readback), symbolic fill (sorted
-columns) and numeric (ordered LDS hash accumulation). Inputs are resident in
-HBM before timing starts; output buffers are reused between steps.
+Headline workload: C = A*A with A the 27-point stencil on a 128^3 grid
+(2,097,152 rows, 55,742,968 entries), fp64 values: diagonal 26, off-diagonals
+-(1 + U(-0.1, 0.1)) (seed 2), int32 CSR indices. One step is one pass of the
+whole plain path in HBM: symbolic count (binning, column compression, LDS hash
+union, scan, nnz readback), symbolic fill (sorted columns) and numeric
+(ordered LDS hash accumulation). Inputs are resident in HBM before timing;
+output buffers are reused between steps.
 
-Prints one JSON line. ``value`` = 2 * multiply-adds / (time per step), in
-GFLOP/s. ``roofline`` covers the dominant kernel (the numeric LDS kernel of
-the class holding the rows), timed with HIP events on its own stream by the
-library's profiling option; its algorithmic bytes are the compulsory bytes
-of the numeric phase (A, B and C's structure read once, C's values written
-once). ``cpu_baseline`` times the CPU oracle on the same product.
+Printed as one JSON line. ``value`` = 2 * multiply-adds / time per step
+(GFLOP/s). ``roofline`` covers the dominant kernel, the numeric LDS kernel of
+the class holding the rows, timed with HIP events on its own stream (the
+library's profiling option); its algorithmic bytes are the compulsory bytes of
+the numeric phase (A, B and C's structure read once, C's values written
+once). ``traffic`` is read from the committed rocprofv3 counter summary when
+it was taken on the current kernel source, else null. ``cpu_baseline`` times
+the CPU oracle on every 8th row of the same product.
+
+The other parts of the metric are measured too (``extras``), unless --quick:
+  chunked  : the numeric phase with A, B, C in pinned host memory under HBM
+             budgets of 8 GB, 2 GB and 512 MB (double-buffered, pipelined),
+             end to end including copies, against the in-HBM numeric phase;
+  batched  : 256 Galerkin products Ac = P^T (A P) on 7-point Laplacians
+             (n ~ U{16..64}, seed 4): batched two-stage pipeline and numeric
+             graph replay against 256 separate calls per stage;
+  backward : 1M x 1M random CSR, Poisson(8) rows (seeds 5, 6; W seed 7):
+             forward numeric, fused adjoint, and the unfused per-call adjoint.
+--workload tc prints a separate line for triangle counting on R-MAT.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
@@ -21,6 +34,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +46,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "num_lds_stencil27_128_traffic.txt")
 
 
 def log(msg):
@@ -42,6 +57,32 @@ def csr_bytes(nrows, nnz):
     return 4 * (nrows + 1) + 12 * nnz
 
 
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("k_numeric.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1804_00695_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per launch of the numeric kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def profile_table(mls):
     n = mls.lib.spgemm_profile_read(None, 0)
     arr = (mls._abi.ProfileEntry * max(n, 1))()
@@ -49,8 +90,19 @@ def profile_table(mls):
     return {arr[i].name.decode(): (arr[i].calls, arr[i].total_ms) for i in range(n)}
 
 
-def cpu_baseline(A, madds_total, budget_s=20.0):
-    """Oracle on rows sampled across the matrix, all host threads (<= 16)."""
+def timed(torch, fn, reps):
+    """Median and best of per-repetition times (ms), each bracketed by syncs."""
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(out)), float(np.min(out))
+
+
+def cpu_baseline(A):
     import oracle
     threads = min(16, os.cpu_count() or 1)
     stride = 8
@@ -60,10 +112,147 @@ def cpu_baseline(A, madds_total, budget_s=20.0):
     dt = time.perf_counter() - t0
     w = oracle.row_work(A, A)
     madds = int(w[rows].sum())
-    return {"value": 2.0 * madds / dt / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+    return {"value": round(2.0 * madds / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"rows 0::{stride} of the same product ({len(rows)} rows, {madds} multiply-adds), "
-                      f"dense-accumulator oracle (C, OpenMP), {dt:.2f} s"}
+                      f"dense-accumulator oracle in C with OpenMP, {dt:.2f} s"}
 
+
+# ---------------------------------------------------------------------------
+
+def bench_chunked(torch, mls, A, C_host_rp, C_host_ci, ms_numeric_hbm):
+    """Chunked numeric phase, end to end (copies included), for several budgets."""
+    Ah = mls.HostCsr.from_host(A)
+    nnzC = len(C_host_ci)
+    Ch = mls.HostCsr(A.nrows, A.ncols, torch.from_numpy(C_host_rp).pin_memory(),
+                     torch.from_numpy(C_host_ci).pin_memory(), torch.empty(nnzC, dtype=torch.float64).pin_memory())
+    streams = mls.ChunkStreams()
+    ws = mls.Workspace()
+    out = {}
+    for label, budget in (("8GB", 8 << 30), ("2GB", 2 << 30), ("512MB", 512 << 20)):
+        plan = mls.chunked_plan(A.row_ptr, A.row_ptr, A.ncols, C_host_rp, budget, nbuf=2, min_parts=4)
+        info = plan.info
+        med, best = timed(torch, lambda: mls.numeric_chunked(Ah, Ah, Ch, plan, ws, streams), 3)
+        moved = info["issued_h2d"] + info["issued_d2h"]
+        out[label] = {"ms": round(med, 2), "best_ms": round(best, 2), "slowdown_vs_hbm": round(med / ms_numeric_hbm, 2),
+                      "algo": f"chunk{info['algo']}", "branch": info["branch"], "parts_ac": info["n_ac_parts"],
+                      "parts_b": info["n_b_parts"], "h2d_GB": round(info["h2d_bytes"] / 1e9, 3),
+                      "d2h_GB": round(info["d2h_bytes"] / 1e9, 3), "pcie_GBs": round(moved / (med * 1e-3) / 1e9, 1)}
+        log(f"chunked {label}: {out[label]}")
+    return out
+
+
+def bench_batched(torch, mls, synth):
+    sizes = synth.amg_batch_sizes(256, 16, 64, seed=4)
+    cache = {}
+    for n in sorted(set(int(x) for x in sizes)):
+        A, P, R = synth.amg_instance(n)
+        cache[n] = tuple(mls.DeviceCsr.from_host(M) for M in (A, P, R))
+    As = [cache[int(n)][0] for n in sizes]
+    Ps = [cache[int(n)][1] for n in sizes]
+    Rs = [cache[int(n)][2] for n in sizes]
+    ws = mls.Workspace()
+
+    def per_call():
+        for a, p, r in zip(As, Ps, Rs):
+            ap = mls.spgemm(a, p, ws)
+            mls.spgemm(r, ap, ws)
+
+    def batched():
+        APs = mls.batch_symbolic(As, Ps, ws)
+        mls.batch_numeric(As, Ps, APs, ws)
+        Acs = mls.batch_symbolic(Rs, APs, ws)
+        mls.batch_numeric(Rs, APs, Acs, ws)
+        return APs, Acs
+
+    per_call()
+    t_call, _ = timed(torch, per_call, 3)
+    APs, Acs = batched()
+    t_batch, _ = timed(torch, batched, 3)
+    plan1 = mls.BatchPlan(As, Ps, APs)
+    plan2 = mls.BatchPlan(Rs, APs, Acs)
+
+    def replay():
+        plan1.run()
+        plan2.run()
+
+    replay()
+    t_replay, _ = timed(torch, replay, 5)
+
+    def numeric_per_call():
+        for a, p, r, ap, ac in zip(As, Ps, Rs, APs, Acs):
+            mls.numeric(a, p, ap, ws)
+            mls.numeric(r, ap, ac, ws)
+
+    numeric_per_call()
+    t_num_call, _ = timed(torch, numeric_per_call, 3)
+    madds = 0
+    # multiply-adds per distinct size, counted once per instance
+    per_n = {}
+    for n in set(int(x) for x in sizes):
+        a, p, r = cache[n]
+        _, w1 = mls.row_work(a, p, ws)
+        ap = mls.spgemm(a, p, ws)
+        _, w2 = mls.row_work(r, ap, ws)
+        per_n[n] = w1 + w2
+    madds = sum(per_n[int(n)] for n in sizes)
+    res = {"instances": 256, "multiply_adds": int(madds),
+           "per_call_ms": round(t_call, 2), "batched_ms": round(t_batch, 2),
+           "speedup_batched_vs_per_call": round(t_call / t_batch, 2),
+           "numeric_per_call_ms": round(t_num_call, 2), "numeric_graph_replay_ms": round(t_replay, 3),
+           "speedup_replay_vs_numeric_per_call": round(t_num_call / t_replay, 2),
+           "autotuned_group_size": [plan1.group_size, plan2.group_size],
+           "replay_gflops": round(2.0 * madds / (t_replay * 1e-3) / 1e9, 1)}
+    log(f"batched: {res}")
+    return res
+
+
+def bench_backward(torch, mls, synth):
+    n = 1_000_000
+    A = synth.poisson_csr(n, n, 8.0, 5)
+    B = synth.poisson_csr(n, n, 8.0, 6)
+    dA, dB = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B)
+    ws = mls.Workspace()
+    C = mls.symbolic(dA, dB, ws)
+    torch.cuda.synchronize()
+    W = mls.DeviceCsr(C.nrows, C.ncols, C.row_ptr, C.col_idx,
+                      torch.from_numpy(synth.normal_values(C.nnz, 7)).cuda())
+    _, madds = mls.row_work(dA, dB, ws)
+    fwd = lambda: mls.numeric(dA, dB, C, ws)
+    bwd = lambda: mls.backward(dA, dB, W, ws=ws)
+    unf = lambda: mls.backward_unfused(dA, dB, W, ws)
+    fwd(); bwd()
+    t_f, _ = timed(torch, fwd, 5)
+    t_b, _ = timed(torch, bwd, 5)
+    unf()
+    t_u, _ = timed(torch, unf, 2)
+    res = {"rows": n, "nnz_A": A.nnz, "nnz_B": B.nnz, "nnz_C": C.nnz, "multiply_adds": int(madds),
+           "forward_ms": round(t_f, 3), "fused_backward_ms": round(t_b, 3),
+           "fwd_plus_bwd_over_fwd": round((t_f + t_b) / t_f, 2),
+           "unfused_per_call_backward_ms": round(t_u, 2),
+           "speedup_fused_vs_unfused": round(t_u / t_b, 1)}
+    log(f"backward: {res}")
+    return res
+
+
+def bench_tc(torch, mls, synth, scale):
+    log(f"generating R-MAT scale {scale}")
+    G = synth.rmat_graph(scale, 16, seed=3)
+    t0 = time.perf_counter()
+    perm, (n, lrp, lci) = mls.tc_lower(G)
+    t_pre = time.perf_counter() - t0
+    L = mls.DeviceCsr.from_host(synth.Csr(n, n, lrp, lci, None))
+    ws = mls.Workspace()
+    mls.triangle_count(L, ws)
+    med, best = timed(torch, lambda: mls.triangle_count(L, ws), 5)
+    _, total = mls.triangle_count(L, ws)
+    return {"metric": "triangle counting time (masked L*compressed(L)), R-MAT", "value": round(med, 3), "unit": "ms",
+            "higher_is_better": False, "n_gpus": 1, "best_ms": round(best, 3), "triangles": int(total),
+            "config": {"workload": f"R-MAT scale {scale}, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 3",
+                       "vertices": n, "edges": int(len(lci))},
+            "host_preprocessing_s": round(t_pre, 2), "dtype": "int64", "data": "synthetic"}
+
+
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
@@ -71,7 +260,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128, help="grid edge (128 = the headline workload)")
-    ap.add_argument("--quick", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--quick", action="store_true", help="headline only: no extras, no CPU baseline")
+    ap.add_argument("--workload", default="spgemm", choices=["spgemm", "tc"])
+    ap.add_argument("--tc-scale", type=int, default=22)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -83,13 +274,17 @@ def main():
     import paper_1804_00695_amd as mls
 
     torch.cuda.set_device(0)
+    if args.workload == "tc":
+        print(json.dumps(bench_tc(torch, mls, synth, args.tc_scale)), flush=True)
+        return
+
     n = args.n
     log(f"generating 27-point stencil {n}^3")
     A = synth.stencil27_3d(n, amp=0.1, seed=2)
     madds = (9 * (n - 2) + 8) ** 3
     nnzC = (5 * n - 6) ** 3
     dA = mls.DeviceCsr.from_host(A)
-    lib, ctypes_ = mls.lib, ctypes
+    lib = mls.lib
     hA = dA.handle()
     wsz = mls.workspace_size(dA, dA)
     ws_t = torch.empty(wsz + 256, dtype=torch.uint8, device="cuda")
@@ -97,8 +292,7 @@ def main():
     crp = torch.empty(A.nrows + 1, dtype=torch.int32, device="cuda")
     cci = torch.empty(nnzC, dtype=torch.int32, device="cuda")
     cval = torch.empty(nnzC, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
-    sh = stream.cuda_stream
+    sh = torch.cuda.current_stream().cuda_stream
     nnz_out = ctypes.c_int64(0)
     hC = mls.CsrT(A.nrows, A.ncols, nnzC, crp.data_ptr(), cci.data_ptr(), cval.data_ptr())
 
@@ -117,7 +311,7 @@ def main():
     torch.cuda.synchronize()
     mls.check(lib.spgemm_check_errors(ws, wsz, sh), "errors")
 
-    # timed region: K steps, profiling events on (one pair per launch)
+    # timed region: K steps, with the profiling event pairs on
     lib.spgemm_profile_reset()
     mls.set_option(mls._abi.OPT_PROFILE, 1)
     torch.cuda.synchronize()
@@ -130,24 +324,19 @@ def main():
     prof = profile_table(mls)
     ms_step = (t1 - t0) * 1e3 / args.steps
 
-    # numeric-only timing (no profiling events), for the numeric GFLOP/s
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        mls.check(lib.spgemm_numeric(ctypes.byref(hA), ctypes.byref(hA), ctypes.byref(hC), ws, wsz, sh), "numeric")
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_numeric = ev0.elapsed_time(ev1) / args.steps
+    # numeric phase alone (no profiling events)
+    ms_numeric, best_numeric = timed(torch, lambda: mls.check(
+        lib.spgemm_numeric(ctypes.byref(hA), ctypes.byref(hA), ctypes.byref(hC), ws, wsz, sh), "numeric"),
+        max(args.steps, 5))
 
-    # dominant kernel
     num_kernels = {k: v for k, v in prof.items() if k.startswith("num_")}
-    dom = max(num_kernels.items(), key=lambda kv: kv[1][1])
-    dom_name, (dom_calls, dom_total) = dom
+    dom_name, (dom_calls, dom_total) = max(num_kernels.items(), key=lambda kv: kv[1][1])
     dom_ms = dom_total / dom_calls
     compulsory = csr_bytes(A.nrows, A.nnz) * 2 + csr_bytes(A.nrows, nnzC)
     model = csr_bytes(A.nrows, A.nnz) + 8 * A.nnz + 12 * madds + csr_bytes(A.nrows, nnzC)
     achieved = compulsory / (dom_ms * 1e-3) / 1e9
     kernels = {k: {"calls": c, "avg_ms": round(t / c, 4)} for k, (c, t) in sorted(prof.items())}
+    sym_ms = sum(t for k, (c, t) in prof.items() if k.startswith("sym_")) / args.steps
 
     result = {
         "metric": "SpGEMM GFLOP/s (2 flops per multiply-add), two-phase C=A*A, all in HBM",
@@ -166,15 +355,38 @@ def main():
                    "nnz_A": A.nnz, "nnz_C": nnzC, "multiply_adds": madds, "parallelism": "none (1 GPU)"},
         "numeric_ms": round(ms_numeric, 4),
         "numeric_gflops": round(2.0 * madds / (ms_numeric * 1e-3) / 1e9, 2),
+        "symbolic_kernels_ms": round(sym_ms, 4),
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": committed_traffic() if n == 128 else None,
                      "kernel_avg_ms": round(dom_ms, 4), "algorithmic_bytes": compulsory,
                      "model_bytes": model, "model_frac": round(model / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": kernels,
     }
     if not args.quick:
+        extras = {}
+        log("chunked")
+        try:
+            rp, ci, _ = mls.DeviceCsr(A.nrows, A.ncols, crp, cci, None).numpy()
+            extras["chunked"] = bench_chunked(torch, mls, A, rp, ci, ms_numeric)
+        except Exception as e:  # report, keep the line
+            extras["chunked"] = {"error": repr(e)}
+        del ws_t, cci, cval
+        torch.cuda.empty_cache()
+        log("batched")
+        try:
+            extras["batched"] = bench_batched(torch, mls, synth)
+        except Exception as e:
+            extras["batched"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        log("backward")
+        try:
+            extras["backward"] = bench_backward(torch, mls, synth)
+        except Exception as e:
+            extras["backward"] = {"error": repr(e)}
+        result["extras"] = extras
         log("cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(A, madds)
+        result["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(result), flush=True)
 
 
