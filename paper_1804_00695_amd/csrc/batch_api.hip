@@ -120,14 +120,19 @@ spgemm_status spgemm_batch_plan_create(int32_t nbatch, const spgemm_csr *A, cons
         // one eager run first: the launch shapes are set up outside the capture
         launch_run(*P, s);
         hipError_t e = hipStreamSynchronize(s);
+        // capture on a private stream (the caller's may be the legacy null
+        // stream, which cannot be captured); the graph replays on any stream
+        hipStream_t cs = nullptr;
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         const bool prof = g_opt.profile;   // no event records inside the captured graph
         g_opt.profile = false;
-        if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            launch_run(*P, s);
-            e = hipStreamEndCapture(s, &P->graph);
+            launch_run(*P, cs);
+            e = hipStreamEndCapture(cs, &P->graph);
         }
         g_opt.profile = prof;
+        if (cs) hipStreamDestroy(cs);
         if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             if (P->graph) hipGraphDestroy(P->graph);
