@@ -154,49 +154,39 @@ __device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
     return s;
 }
 
-// Per-wave dynamic task fetch. Tasks of a bin are split into one contiguous
-// slab per XCD (workgroup w runs on XCD w % 8), so neighbouring rows -- which
-// share rows of B -- are processed by CUs sharing one L2. A wave takes
-// `chunk` consecutive tasks per atomic (about 16 grabs per wave over the
-// bin), drains its own XCD's slab and then helps the others. Returns -1 when
-// all are done. Must be called by all lanes of the wave (uniform control).
+// Per-wave task schedule. Tasks of a bin are split into one contiguous slab
+// per XCD (workgroup w runs on XCD w % 8, and the CUs of an XCD share one L2).
+// Inside a slab the waves of that XCD take tasks round-robin, so at any time
+// the rows in flight on an XCD form a narrow window of consecutive tasks:
+// neighbouring rows share most of their rows of B, and a narrow window keeps
+// that shared working set inside the L2. No atomics are involved.
 struct TaskIter {
-    int xcd;
-    int probe;   // how many slabs tried
-    int cur, end;
-    int chunk;
+    int next, hi, stride;
 };
 
 __device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg)
 {
+    const int x = (int)(blockIdx.x % kXcd);
+    const int lo = (int)(((int64_t)ntasks * x) / kXcd);
+    const int hi = (int)(((int64_t)ntasks * (x + 1)) / kXcd);
+    const int wgs_x = ((int)gridDim.x - x + kXcd - 1) / kXcd;   // workgroups on this XCD
+    const int wave = (int)(threadIdx.x >> 6);
     TaskIter it;
-    it.xcd = (int)(blockIdx.x % kXcd);
-    it.probe = 0;
-    it.cur = it.end = 0;
-    int64_t waves = (int64_t)gridDim.x * waves_per_wg;
-    int64_t c = ntasks / (waves * 16);
-    it.chunk = (int)(c < 1 ? 1 : (c > 256 ? 256 : c));
+    it.next = lo + (int)(blockIdx.x / kXcd) * waves_per_wg + wave;
+    it.hi = hi;
+    it.stride = wgs_x * waves_per_wg;
     return it;
 }
 
+// Next task of this wave, or -1. Uniform across the wave.
 __device__ __forceinline__ int next_task_wave(int32_t *cursor, int ntasks, TaskIter &it)
 {
-    if (it.cur < it.end) return it.cur++;
-    while (it.probe < kXcd) {
-        int x = (it.xcd + it.probe) & (kXcd - 1);
-        int lo = (int)(((int64_t)ntasks * x) / kXcd);
-        int hi = (int)(((int64_t)ntasks * (x + 1)) / kXcd);
-        int t = 0;
-        if ((threadIdx.x & (kWave - 1)) == 0) t = atomicAdd(cursor + x, it.chunk);
-        t = __shfl(t, 0, kWave);
-        if (lo + t < hi) {
-            it.cur = lo + t;
-            it.end = min(hi, lo + t + it.chunk);
-            return it.cur++;
-        }
-        ++it.probe;
-    }
-    return -1;
+    (void)cursor;
+    (void)ntasks;
+    if (it.next >= it.hi) return -1;
+    const int t = it.next;
+    it.next += it.stride;
+    return t;
 }
 
 }  // namespace mls

@@ -26,7 +26,7 @@
 
 namespace mls {
 
-constexpr int kUnroll = 4;
+constexpr int kNumDepth = 8;   // steps whose B loads are issued together
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -70,9 +70,10 @@ template <int G, int CAP>
 __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_num(CAP * 12, W);
+    constexpr int NW = nw_num(CAP * 12 + G * 16, W);
     __shared__ int2 s_tab[NW * W * CAP];
     __shared__ double s_acc[NW * W * (CAP / 2)];
+    __shared__ int4 s_par[NW * W * G];   // staged entries of row i of A: (q0, q1, a)
 
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
     const int rs = wave * W + slot;
     int2 *tab = s_tab + rs * CAP;
     double *acc = s_acc + rs * (CAP / 2);
+    int4 *par = s_par + rs * G;
 
     const MLS_G int32_t *perm = gp(sc.perm);
     const MLS_G int32_t *val = gp(sc.val);
@@ -124,48 +126,60 @@ __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
             }
         }
         nwave_sync();
-        if (active) {
-            bool bad = false;
-            for (int p = ps; p < pe; p += kUnroll) {
-                double av[kUnroll], bv[kUnroll];
-                int q0[kUnroll], q1[kUnroll], jv[kUnroll];
+        bool bad = false;
+        for (int pc = ps; pc < pe; pc += G) {
+            // stage a chunk of row i of A: one round of loads for G entries
+            {
+                const int p = pc + lane;
+                int q0 = 0, q1 = 0;
+                double a = 0.0;
+                if (p < pe) {
+                    const int k = aci[p];
+                    a = aval[p];
+                    if (k >= k_lo && k < k_hi) {
+                        q0 = brp[k - k_lo] - b_off;
+                        q1 = brp[k - k_lo + 1] - b_off;
+                    }
+                }
+                par[lane] = make_int4(q0, q1, __double2loint(a), __double2hiint(a));
+            }
+            nwave_sync();
+            const int n = min(G, pe - pc);
+            for (int u0 = 0; u0 < n; u0 += kNumDepth) {
+                // issue the B loads of kNumDepth steps, then accumulate them in order
+                int jv[kNumDepth], q1v[kNumDepth];
+                double bv[kNumDepth], av[kNumDepth];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    q0[u] = 0; q1[u] = 0; av[u] = 0.0;
-                    if (p + u < pe) {
-                        int k = aci[p + u];
-                        av[u] = aval[p + u];
-                        if (k >= k_lo && k < k_hi) {
-                            int kl = k - k_lo;
-                            q0[u] = brp[kl] - b_off;
-                            q1[u] = brp[kl + 1] - b_off;
+                for (int d = 0; d < kNumDepth; ++d) {
+                    jv[d] = -1; bv[d] = 0.0; av[d] = 0.0; q1v[d] = 0;
+                    if (u0 + d < n) {
+                        const int4 pr = par[u0 + d];
+                        av[d] = __hiloint2double(pr.w, pr.z);
+                        q1v[d] = pr.y;
+                        const int q = pr.x + lane;
+                        if (q < pr.y) { jv[d] = bci[q]; bv[d] = bval[q]; }
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < kNumDepth; ++d) {
+                    if (jv[d] >= 0) {
+                        const int pos = pos_lookup(tab, logcap, jv[d]);
+                        if (pos >= 0) acc[pos] = acc[pos] + av[d] * bv[d];
+                        else bad = true;
+                    }
+                    if (u0 + d < n) {   // rows of B longer than G: the rest of this step
+                        const int q0 = par[u0 + d].x;
+                        for (int q = q0 + G + lane; q < q1v[d]; q += G) {
+                            const int pos = pos_lookup(tab, logcap, bci[q]);
+                            if (pos >= 0) acc[pos] = acc[pos] + av[d] * bval[q];
+                            else bad = true;
                         }
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    int q = q0[u] + lane;
-                    jv[u] = -1; bv[u] = 0.0;
-                    if (q < q1[u]) { jv[u] = bci[q]; bv[u] = bval[q]; }
-                }
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (jv[u] >= 0) {
-                        int pos = pos_lookup(tab, logcap, jv[u]);
-                        if (pos >= 0) acc[pos] = acc[pos] + av[u] * bv[u];
-                        else bad = true;
-                    }
-                    for (int q = q0[u] + G + lane; q < q1[u]; q += G) {
-                        int j = bci[q];
-                        int pos = pos_lookup(tab, logcap, j);
-                        if (pos >= 0) acc[pos] = acc[pos] + av[u] * bval[q];
-                        else bad = true;
-                    }
-                }
             }
-            if (bad) atomicOr(sc.err, kErrStructure);
+            nwave_sync();
         }
-        nwave_sync();
+        if (bad) atomicOr(sc.err, kErrStructure);
         if (active)
             for (int e = lane; e < nc; e += G) cval[cs + e] = acc[e];
         nwave_sync();
@@ -244,7 +258,7 @@ template <int G, int CAP>
 static void launch_num_class(const Batch &b, const Sched &sc, int bin, hipStream_t s)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_num(CAP * 12, W);
+    constexpr int NW = nw_num(CAP * 12 + G * 16, W);
     static int grid = persistent_grid_n(k_num_lds<G, CAP>, NW * kWave);
     static char name[64];
     if (!name[0]) snprintf(name, sizeof(name), "num_lds_G%d_C%d", G, CAP);

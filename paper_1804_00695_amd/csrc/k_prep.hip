@@ -25,70 +25,145 @@ __global__ void k_fill_f64(double *p, double v, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
+// Row-cooperative helpers: 32 lanes share a row and read its entries in
+// coalesced chunks of 32; 8 rows per 256-thread workgroup.
+
+constexpr int kRowG = 32;
+constexpr int kRowsPerWG = kWG / kRowG;
+
+__device__ __forceinline__ uint32_t group_ballot(bool pred, int slot_in_wave)
+{
+    // 64-bit wave ballot, cut to the 32 lanes of this row group
+    unsigned long long b = __ballot(pred);
+    return (uint32_t)(b >> (32 * slot_in_wave));
+}
+
 // CSR checks over the A rows (which = 0) or B rows (which = 1) of a batch:
 // row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, columns in range and
-// strictly increasing.
-
-__global__ void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
+// strictly increasing. Column indices outside [0, nnz) are never read.
+__global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
 {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    int total = which == 0 ? b.na : b.nb;
-    if (g >= total) return;
+    const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
+    const int g = blockIdx.x * kRowsPerWG + slot;
+    const int total = which == 0 ? b.na : b.nb;
+    if (g >= total) return;   // whole row groups leave together (g is uniform per group)
     const int32_t *base = which == 0 ? b.abase : b.bbase;
-    int t = b.nprob == 1 ? 0 : find_prob(base, b.nprob, g);
+    const int t = b.nprob == 1 ? 0 : find_prob(base, b.nprob, g);
     const Prob P = get_prob(b, t);
-    int i = g - (b.nprob == 1 ? 0 : gp(base)[t]);
+    const int i = g - (b.nprob == 1 ? 0 : gp(base)[t]);
     const MLS_G int32_t *rp = gp(which == 0 ? P.arp : P.brp);
     const MLS_G int32_t *ci = gp(which == 0 ? P.aci : P.bci);
-    int off = which == 0 ? P.a_off : P.b_off;
-    int ncols = which == 0 ? P.k_hi : P.ncols;
-    int nrows = which == 0 ? P.nrows : P.krows;
-    bool bad = false;
+    const int off = which == 0 ? P.a_off : P.b_off;
+    const int ncols = which == 0 ? P.k_hi : P.ncols;
+    const int nrows = which == 0 ? P.nrows : P.krows;
     const int64_t nnz = gp(nnz_tab)[2 * t + which];
-    int s = rp[i], e = rp[i + 1];
+    const int s = rp[i], e = rp[i + 1];
+    bool bad = false;
     if (i == 0 && s != off) bad = true;
     if (i == nrows - 1 && (int64_t)e - off != nnz) bad = true;
-    // never read column indices outside [0, nnz)
     if (e < s || s < off || (int64_t)e - off > nnz) bad = true;
     if (!bad) {
-        int prev = -1;
-        for (int q = s - off; q < e - off; ++q) {
-            int c = ci[q];
-            if (c < 0 || c >= ncols || c <= prev) { bad = true; break; }
-            prev = c;
+        int carry = -1;
+        for (int q0 = s - off; q0 < e - off; q0 += kRowG) {
+            const int q = q0 + lane;
+            const bool valid = q < e - off;
+            const int c = valid ? ci[q] : 0;
+            int prev = __shfl_up(c, 1, kRowG);
+            if (lane == 0) prev = carry;
+            if (valid && (c < 0 || c >= ncols || c <= prev)) bad = true;
+            carry = __shfl(c, kRowG - 1, kRowG);
         }
     }
     if (bad) atomicOr(err, kErrBadCsr);
 }
 
-// ---------------------------------------------------------------------------
 // Column compression of every B row (set = col >> 5, mask bit = col & 31),
 // padded layout: the words of row k start at B's entry offset of row k.
-
-__global__ void k_compress(Batch b)
+// Chunks of 32 entries: a lane starts a word where its set differs from the
+// previous entry's; masks are OR-ed in LDS; the last word of a chunk stays
+// open (it may continue in the next chunk).
+__global__ __launch_bounds__(kWG) void k_compress(Batch b)
 {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= b.nb) return;
-    int t = b.nprob == 1 ? 0 : find_prob(b.bbase, b.nprob, g);
-    const Prob P = get_prob(b, t);
-    int k = g - (b.nprob == 1 ? 0 : gp(b.bbase)[t]);
-    int s = gp(P.brp)[k] - P.b_off, e = gp(P.brp)[k + 1] - P.b_off;
-    MLS_G u32x2 *__restrict__ out = (MLS_G u32x2 *)P.bw + s;
-    const MLS_G int32_t *__restrict__ bci = gp(P.bci);
-    int n = 0;
-    uint32_t cur = 0xffffffffu, mask = 0;
-    for (int q = s; q < e; ++q) {
-        uint32_t c = (uint32_t)bci[q];
-        uint32_t set = c >> 5;
-        if (set != cur) {
-            if (cur != 0xffffffffu) { u32x2 w; w.x = cur; w.y = mask; out[n++] = w; }
-            cur = set;
-            mask = 0;
-        }
-        mask |= 1u << (c & 31u);
+    __shared__ uint32_t s_set[kRowsPerWG][kRowG + 1];
+    __shared__ uint32_t s_msk[kRowsPerWG][kRowG + 1];
+    const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
+    const int wslot = slot & 1;   // which half of the 64-lane wave
+    const int g = blockIdx.x * kRowsPerWG + slot;
+    const bool row_ok = g < b.nb;
+    int t = 0, k = 0;
+    Prob P = b.p0;
+    if (row_ok) {
+        t = b.nprob == 1 ? 0 : find_prob(b.bbase, b.nprob, g);
+        P = get_prob(b, t);
+        k = g - (b.nprob == 1 ? 0 : gp(b.bbase)[t]);
     }
-    if (cur != 0xffffffffu) { u32x2 w; w.x = cur; w.y = mask; out[n++] = w; }
-    gpw(P.bwc)[k] = n;
+    const int s = row_ok ? gp(P.brp)[k] - P.b_off : 0;
+    const int e = row_ok ? gp(P.brp)[k + 1] - P.b_off : 0;
+    const MLS_G int32_t *__restrict__ bci = gp(P.bci);
+    MLS_G u32x2 *__restrict__ out = (MLS_G u32x2 *)P.bw + s;
+    uint32_t *wset = s_set[slot], *wmsk = s_msk[slot];
+    const uint32_t kNone = 0xffffffffu;
+    uint32_t carry_set = kNone, carry_msk = 0;
+    int nout = 0;
+    // every group of the wave runs the same number of chunks (shuffles need all lanes)
+    int len = e - s;
+    int maxlen = max(len, __shfl_xor(len, 32, kWave));
+    for (int c0 = 0; c0 < maxlen; c0 += kRowG) {
+        const int q = s + c0 + lane;
+        const bool valid = c0 + lane < len;
+        const uint32_t c = valid ? (uint32_t)bci[q] : 0u;
+        const uint32_t set = valid ? (c >> 5) : kNone;
+        uint32_t prev = __shfl_up(set, 1, kRowG);
+        if (lane == 0) prev = carry_set;
+        const bool head = valid && set != prev;
+        const uint32_t hm = group_ballot(head, wslot);
+        const int lw = __popc(hm & ((2u << lane) - 1u));   // 0 = continues the open word
+        wmsk[lane] = 0u;
+        if (lane == 0) wmsk[kRowG] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (valid) {
+            atomicOr(&wmsk[lw], 1u << (c & 31u));
+            if (head) wset[lw] = set;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const int nh = __popc(hm);
+        if (row_ok && c0 < len) {
+            // word 0 continues the open word; words 1..nh-1 are complete; word nh stays open
+            if (nh > 0 && carry_set != kNone && lane == 0) {
+                u32x2 w; w.x = carry_set; w.y = carry_msk | wmsk[0];
+                out[nout] = w;
+            }
+            const int base_out = nout + (carry_set != kNone ? 1 : 0);
+            if (lane >= 1 && lane < nh) {
+                u32x2 w; w.x = wset[lane]; w.y = wmsk[lane];
+                out[base_out + lane - 1] = w;
+            }
+        }
+        if (nh > 0) {
+            nout += (carry_set != kNone ? 1 : 0) + nh - 1;
+            carry_set = wset[nh];
+            carry_msk = wmsk[nh];
+        } else {
+            carry_msk |= wmsk[0];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    if (row_ok) {
+        if (carry_set != kNone) {
+            if (lane == 0) {
+                u32x2 w; w.x = carry_set; w.y = carry_msk;
+                out[nout] = w;
+            }
+            ++nout;
+        }
+        if (lane == 0) gpw(P.bwc)[k] = nout;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -114,49 +189,56 @@ __device__ __forceinline__ int class_of(int mode, int64_t size, int force_spill)
     return kBinSpill;
 }
 
-__global__ void k_bin(Batch b, int mode, Sched sc, int force_spill, unsigned long long *total)
+constexpr int kBinRowsPerWG = 256;   // rows per workgroup: one set of global atomics each
+
+__global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int force_spill,
+                                             unsigned long long *total)
 {
     __shared__ int cnt[kNumBins];
     __shared__ unsigned long long tsum;
     if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) tsum = 0;
     __syncthreads();
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < b.na) {
-        int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+    const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
+    for (int r = slot; r < kBinRowsPerWG; r += kRowsPerWG) {
+        const int g = blockIdx.x * kBinRowsPerWG + r;
+        if (g >= b.na) break;   // uniform per row group
+        const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
         const Prob P = get_prob(b, t);
-        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
         int64_t size = 0;
-        int64_t nc = 0;
-        if (mode != kModeWork && mode != kModeCount) nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
         if (mode != kModeNumeric) {
             const MLS_G int32_t *__restrict__ aci = gp(P.aci);
             const MLS_G int32_t *__restrict__ brp = gp(P.brp);
             const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
             const int k_lo = P.k_lo, k_hi = P.k_hi;
-            int s = gp(P.arp)[i] - P.a_off, e = gp(P.arp)[i + 1] - P.a_off;
-            for (int p = s; p < e; ++p) {
-                int k = aci[p];
+            const int s = gp(P.arp)[i] - P.a_off, e = gp(P.arp)[i + 1] - P.a_off;
+            for (int p = s + lane; p < e; p += kRowG) {
+                const int k = aci[p];
                 if (k < k_lo || k >= k_hi) continue;
-                int kl = k - k_lo;
-                if (mode == kModeWork) size += brp[kl + 1] - brp[kl];
-                else size += bwc[kl];
+                const int kl = k - k_lo;
+                size += mode == kModeWork ? (int64_t)(brp[kl + 1] - brp[kl]) : (int64_t)bwc[kl];
             }
+            size = group_sum<kRowG>(size);
         }
-        if (mode == kModeFill) size = size < nc ? size : nc;
-        if (mode == kModeNumeric) size = nc;
-        int c;
-        if (mode == kModeWork) {
-            c = kBinEmpty;
-            if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
-            atomicAdd(&tsum, (unsigned long long)size);
-        } else {
-            c = class_of(mode, size, force_spill);
+        if (lane == 0) {
+            int64_t nc = 0;
+            if (mode == kModeFill || mode == kModeNumeric) nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
+            if (mode == kModeFill) size = size < nc ? size : nc;
+            if (mode == kModeNumeric) size = nc;
+            int c;
+            if (mode == kModeWork) {
+                c = kBinEmpty;
+                if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
+                atomicAdd(&tsum, (unsigned long long)size);
+            } else {
+                c = class_of(mode, size, force_spill);
+            }
             if (size >= 0x7fffffffLL) size = 0x7fffffff;
+            gpw(sc.val)[g] = (int32_t)size;
+            gpw(sc.cls)[g] = (uint8_t)c;
+            atomicAdd(&cnt[c], 1);
         }
-        gpw(sc.val)[g] = (int32_t)size;
-        gpw(sc.cls)[g] = (uint8_t)c;
-        atomicAdd(&cnt[c], 1);
     }
     __syncthreads();
     if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(sc.bin_count + threadIdx.x, cnt[threadIdx.x]);
@@ -308,14 +390,14 @@ void launch_validate(const Batch &b, int which, const int64_t *nnz_tab, uint32_t
     int n = which == 0 ? b.na : b.nb;
     if (n <= 0) return;
     ProfScope ps("validate", s);
-    hipLaunchKernelGGL(k_validate, dim3(nblk(n, kWG)), dim3(kWG), 0, s, b, which, nnz_tab, err);
+    hipLaunchKernelGGL(k_validate, dim3(nblk(n, kRowsPerWG)), dim3(kWG), 0, s, b, which, nnz_tab, err);
 }
 
 void launch_compress(const Batch &b, hipStream_t s)
 {
     if (b.nb <= 0) return;
     ProfScope ps("compress", s);
-    hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kWG)), dim3(kWG), 0, s, b);
+    hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kRowsPerWG)), dim3(kWG), 0, s, b);
 }
 
 void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsigned long long *total,
@@ -324,7 +406,7 @@ void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsi
     if (b.na <= 0) return;
     {
         ProfScope ps("bin", s);
-        hipLaunchKernelGGL(k_bin, dim3(nblk(b.na, kWG)), dim3(kWG), 0, s, b, mode, sc, force_spill, total);
+        hipLaunchKernelGGL(k_bin, dim3(nblk(b.na, kBinRowsPerWG)), dim3(kWG), 0, s, b, mode, sc, force_spill, total);
     }
     ProfScope ps("scatter", s);
     hipLaunchKernelGGL(k_scatter, dim3(nblk(b.na, kWG)), dim3(kWG), 0, s, b.na, sc);

@@ -107,10 +107,15 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
                 if (k < k_lo || k >= k_hi) continue;
                 int kl = k - k_lo;
                 const MLS_G u32x2 *w = bw + (brp[kl] - b_off);
-                int nw = bwc[kl];
-                for (int x = 0; x < nw; ++x) {
-                    u32x2 wd = w[x];
-                    set_insert(key, msk, logcap, wd.x, wd.y, sc.err);
+                const int nw = bwc[kl];
+                for (int x = 0; x < nw; x += 4) {
+                    u32x2 wd[4];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d)
+                        if (x + d < nw) wd[d] = w[x + d];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d)
+                        if (x + d < nw) set_insert(key, msk, logcap, wd[d].x, wd[d].y, sc.err);
                 }
             }
         }
