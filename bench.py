@@ -93,10 +93,13 @@ def profile_table(mls):
     return {arr[i].name.decode(): (arr[i].calls, arr[i].total_ms) for i in range(n)}
 
 
-def timed(torch, fn, reps):
-    """Median and best of per-repetition times (ms), each bracketed by syncs."""
+def timed(torch, fn, reps, pre=None):
+    """Median and best of per-repetition times (ms), each bracketed by syncs;
+    `pre` (untimed) runs before every repetition."""
     out = []
     for _ in range(reps):
+        if pre is not None:
+            pre()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fn()
@@ -105,19 +108,88 @@ def timed(torch, fn, reps):
     return float(np.median(out)), float(np.min(out))
 
 
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(A):
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    stride = 8
-    rows = np.arange(0, A.nrows, stride, dtype=np.int32)
-    t0 = time.perf_counter()
-    oracle.spgemm(A, A, rows=rows, nthreads=threads, with_abs=False)
-    dt = time.perf_counter() - t0
     w = oracle.row_work(A, A)
-    madds = int(w[rows].sum())
+
+    def run(stride, nthreads):
+        rows = np.arange(0, A.nrows, stride, dtype=np.int32)
+        t0 = time.perf_counter()
+        oracle.spgemm(A, A, rows=rows, nthreads=nthreads, with_abs=False)
+        dt = time.perf_counter() - t0
+        madds = int(w[rows].sum())
+        return rows, madds, dt
+
+    rows, madds, dt = run(8, threads)
+    rows1, madds1, dt1 = run(128, 1)
     return {"value": round(2.0 * madds / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"rows 0::{stride} of the same product ({len(rows)} rows, {madds} multiply-adds), "
-                      f"dense-accumulator oracle in C with OpenMP, {dt:.2f} s"}
+            "sample": f"rows 0::8 of the same product ({len(rows)} rows, {madds} multiply-adds), "
+                      f"dense-accumulator oracle in C with OpenMP, {dt:.2f} s",
+            "single_thread_value": round(2.0 * madds1 / dt1 / 1e9, 3),
+            "single_thread_sample": f"rows 0::128 ({len(rows1)} rows, {madds1} multiply-adds), 1 thread, {dt1:.2f} s",
+            "host_cpus": os.cpu_count(), "host_cpu_model": host_cpu_model()}
+
+
+class Flush:
+    """Writes a 512 MB buffer so that the next repetition does not find its
+    inputs in the last-level cache (MALL)."""
+
+    def __init__(self, torch):
+        self.buf = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        self.k = 0
+
+    def __call__(self):
+        self.k = (self.k + 1) & 0xff
+        self.buf.fill_(self.k)
+
+
+def pcie_peak(torch):
+    """Pinned host <-> HBM copy rates (GB/s): each direction alone, then both at
+    once on two streams (1 GiB each)."""
+    nbytes = 1 << 30
+    h_src = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    h_dst = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    d_a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    d_b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def h2d():
+        with torch.cuda.stream(s1):
+            d_a.copy_(h_src, non_blocking=True)
+        s1.synchronize()
+
+    def d2h():
+        with torch.cuda.stream(s2):
+            h_dst.copy_(d_b, non_blocking=True)
+        s2.synchronize()
+
+    def both():
+        with torch.cuda.stream(s1):
+            d_a.copy_(h_src, non_blocking=True)
+        with torch.cuda.stream(s2):
+            h_dst.copy_(d_b, non_blocking=True)
+        s1.synchronize()
+        s2.synchronize()
+
+    h2d(); d2h()
+    t_h, _ = timed(torch, h2d, 3)
+    t_d, _ = timed(torch, d2h, 3)
+    t_b, _ = timed(torch, both, 3)
+    del h_src, h_dst, d_a, d_b
+    return {"h2d_GBs": round(nbytes / (t_h * 1e-3) / 1e9, 1), "d2h_GBs": round(nbytes / (t_d * 1e-3) / 1e9, 1),
+            "duplex_GBs": round(2 * nbytes / (t_b * 1e-3) / 1e9, 1)}
 
 
 # ---------------------------------------------------------------------------
@@ -130,8 +202,9 @@ def bench_chunked(torch, mls, A, C_host_rp, C_host_ci, ms_numeric_hbm):
                      torch.from_numpy(C_host_ci).pin_memory(), torch.empty(nnzC, dtype=torch.float64).pin_memory())
     streams = mls.ChunkStreams()
     ws = mls.Workspace()
-    out = {}
-    for label, budget in (("8GB", 8 << 30), ("2GB", 2 << 30), ("512MB", 512 << 20)):
+    out = {"pcie_peak": pcie_peak(torch)}
+    log(f"pcie peak: {out['pcie_peak']}")
+    for label, budget in (("8GB", 8 << 30), ("2GB", 2 << 30), ("512MB", 512 << 20), ("256MB", 256 << 20)):
         plan = mls.chunked_plan(A.row_ptr, A.row_ptr, A.ncols, C_host_rp, budget, nbuf=2, min_parts=4)
         info = plan.info
         med, best = timed(torch, lambda: mls.numeric_chunked(Ah, Ah, Ch, plan, ws, streams), 3)
@@ -224,13 +297,19 @@ def bench_backward(torch, mls, synth):
     bwd = lambda: mls.backward(dA, dB, W, ws=ws)
     unf = lambda: mls.backward_unfused(dA, dB, W, ws)
     fwd(); bwd()
-    t_f, _ = timed(torch, fwd, 5)
-    t_b, _ = timed(torch, bwd, 5)
+    # B (about 100 MB) fits in the MALL: flush between repetitions
+    flush = Flush(torch)
+    t_f, _ = timed(torch, fwd, 5, pre=flush)
+    t_b, _ = timed(torch, bwd, 5, pre=flush)
+    t_f_warm, _ = timed(torch, fwd, 5)
+    t_b_warm, _ = timed(torch, bwd, 5)
     unf()
-    t_u, _ = timed(torch, unf, 2)
+    t_u, _ = timed(torch, unf, 2, pre=flush)
+    del flush
     res = {"rows": n, "nnz_A": A.nnz, "nnz_B": B.nnz, "nnz_C": C.nnz, "multiply_adds": int(madds),
            "forward_ms": round(t_f, 3), "fused_backward_ms": round(t_b, 3),
            "fwd_plus_bwd_over_fwd": round((t_f + t_b) / t_f, 2),
+           "forward_warm_ms": round(t_f_warm, 3), "fused_backward_warm_ms": round(t_b_warm, 3),
            "unfused_per_call_backward_ms": round(t_u, 2),
            "speedup_fused_vs_unfused": round(t_u / t_b, 1)}
     log(f"backward: {res}")
@@ -335,10 +414,13 @@ def main():
     prof = profile_table(mls)
     ms_step = (t1 - t0) * 1e3 / args.steps
 
-    # numeric phase alone (no profiling events)
+    # numeric phase alone (no profiling events), with the MALL flushed before
+    # every repetition
+    flush = Flush(torch)
     ms_numeric, best_numeric = timed(torch, lambda: mls.check(
         lib.spgemm_numeric(ctypes.byref(hA), ctypes.byref(hA), ctypes.byref(hC), ws, wsz, sh), "numeric"),
-        max(args.steps, 5))
+        max(args.steps, 5), pre=flush)
+    del flush
 
     num_kernels = {k: v for k, v in prof.items() if k.startswith("num_")}
     dom_name, (dom_calls, dom_total) = max(num_kernels.items(), key=lambda kv: kv[1][1])
@@ -369,6 +451,7 @@ def main():
                    "nnz_A": A.nnz, "nnz_C": nnzC, "multiply_adds": madds, "parallelism": "none (1 GPU)"},
         "numeric_ms": round(ms_numeric, 4),
         "numeric_gflops": round(2.0 * madds / (ms_numeric * 1e-3) / 1e9, 2),
+        "numeric_best_ms": round(best_numeric, 4),
         "symbolic_kernels_ms": round(sym_ms, 4),
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -105,8 +105,13 @@ spgemm_status spgemm_validate_host(const spgemm_csr *M_host);
  * Plain product, everything in HBM (Sec. 2.1)
  * --------------------------------------------------------------------- */
 
-/* Minimum workspace for spgemm_row_work, spgemm_compress, spgemm_symbolic
- * and spgemm_numeric on these shapes (only nrows, ncols, nnz are read). */
+/* Workspace for spgemm_row_work, spgemm_compress, spgemm_symbolic and
+ * spgemm_numeric on these shapes (only nrows, ncols, nnz are read). The
+ * size returned includes a per-row scratch (64 words of 8 bytes per row of
+ * A) in which the symbolic count pass keeps each row's compressed column
+ * set for the fill pass; a smaller workspace still works down to the size
+ * without that scratch (the fill pass then recomputes every row), and
+ * below that calls return SPGEMM_ERR_WORKSPACE_TOO_SMALL. */
 spgemm_status spgemm_workspace_size(const spgemm_csr *A, const spgemm_csr *B, size_t *bytes);
 
 /* Row work estimate (the input of row binning): work[i] = number of
@@ -135,6 +140,11 @@ spgemm_status spgemm_compress(const spgemm_csr *B, uint32_t *words, int32_t *cou
  *   fill pass (C_col_idx != NULL): C_row_ptr must hold the count pass's
  *     result; writes the ascending, unique columns of every row of C into
  *     C_col_idx[nnz(C)]. nnzC_host may be NULL. Does not synchronise.
+ *     When it directly follows a count pass on the same operands (same
+ *     pointers, shapes and workspace, and no other call on that workspace
+ *     in between), it reuses the compressed B and the per-row column sets
+ *     that the count pass left in the workspace; A and B must not have
+ *     been modified in between. Otherwise it recomputes them.
  * Errors: SPGEMM_ERR_BAD_CSR, SPGEMM_ERR_DIM_MISMATCH,
  * SPGEMM_ERR_INDEX_OVERFLOW (nnz(C) >= 2^31). */
 spgemm_status spgemm_symbolic(const spgemm_csr *A, const spgemm_csr *B, int32_t *C_row_ptr,

@@ -213,10 +213,11 @@ class Plan:
     def __init__(self, handle, keep):
         self._h = handle
         self._keep = keep
+        self._destroy = lib.spgemm_plan_destroy   # still bound at interpreter exit
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib.spgemm_plan_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     @property
@@ -446,6 +447,7 @@ class BatchPlan:
     def __init__(self, As, Bs, Cs, group_size: int = 0, use_graph: bool = True):
         dev = As[0].row_ptr.device
         self.ws = Workspace(dev)
+        self._destroy = lib.spgemm_batch_plan_destroy   # still bound at interpreter exit
         nb = batch_workspace_size(As, Bs)
         self._keep = (As, Bs, Cs, _handles(As), _handles(Bs), _handles(Cs))
         out = ctypes.c_void_p(0)
@@ -463,5 +465,5 @@ class BatchPlan:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib.spgemm_batch_plan_destroy(self._h)
+            self._destroy(self._h)
             self._h = None

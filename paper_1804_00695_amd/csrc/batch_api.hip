@@ -79,6 +79,7 @@ spgemm_status spgemm_batch_plan_create(int32_t nbatch, const spgemm_csr *A, cons
         if (C[t].nrows != A[t].nrows || C[t].ncols != B[t].ncols) return SPGEMM_ERR_DIM_MISMATCH;
         if (!C[t].row_ptr || (C[t].nnz > 0 && (!C[t].col_idx || !C[t].values))) return SPGEMM_ERR_INVALID_ARG;
     }
+    memo_forget(ws);
     BatchPlanImpl *P = new BatchPlanImpl();
     spgemm_status st = prepare_batch(nbatch, A, B, C, true, false, (char *)ws, ws_bytes, s, P->bh);
     if (st != SPGEMM_OK) { delete P; return st; }

@@ -35,6 +35,7 @@ spgemm_status spgemm_backward(const spgemm_csr *A, const spgemm_csr *B, const sp
 {
     if (!W || !W->row_ptr || (W->nnz > 0 && (!W->col_idx || !W->values))) return SPGEMM_ERR_INVALID_ARG;
     if (!A || !B || W->nrows != A->nrows || W->ncols != B->ncols) return SPGEMM_ERR_DIM_MISMATCH;
+    memo_forget(ws_v);
     BatchHost bh;
     spgemm_status st = prepare_batch(1, A, B, W, true, false, (char *)ws_v, ws_bytes, s, bh);
     if (st != SPGEMM_OK) return st;
@@ -62,6 +63,7 @@ spgemm_status spgemm_transpose(const spgemm_csr *M, spgemm_csr *T, void *ws_v, s
     if (T->nrows != M->ncols || T->ncols != M->nrows || T->nnz != M->nnz) return SPGEMM_ERR_DIM_MISMATCH;
     if (M->values && !T->values && M->nnz > 0) return SPGEMM_ERR_INVALID_ARG;
     if (!ws_v || ws_bytes < transpose_ws(M->ncols) || ((uintptr_t)ws_v & 255)) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
+    memo_forget(ws_v);
     char *w = (char *)ws_v;
     const size_t a = al(4 * (size_t)std::max<int64_t>(M->ncols, 1));
     int32_t *cnt = (int32_t *)w;

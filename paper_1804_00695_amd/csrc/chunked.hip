@@ -118,6 +118,7 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
     if ((int64_t)ws_bytes < P->ws_bytes) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
     if (((uintptr_t)ws_v & 255) != 0) return SPGEMM_ERR_INVALID_ARG;
     char *ws = (char *)ws_v;
+    memo_forget(ws_v);
 
     const Layout L = make_layout(1, A->nrows, B->nrows, 0, B->ncols, false);
     char *buf0 = ws + al(L.total);

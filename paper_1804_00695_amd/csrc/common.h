@@ -81,7 +81,14 @@ struct Sched {
     int32_t *val;           // per global row: size used for binning / result
     uint8_t *cls;           // per global row: bin
     int32_t *perm;          // rows grouped by bin
+    // symbolic scratch: the count pass leaves each row's compacted (set, mask)
+    // words here (up to kScratchWords per row; scnt = -1 when a row has more)
+    // and the fill pass expands them instead of recomputing the union
+    uint2 *scr;             // nullptr when the workspace has no room for it
+    int32_t *scnt;
 };
+
+constexpr int kScratchWords = 64;
 
 // Pointers read out of descriptors are generic; loads through them compile
 // to flat instructions, which make the compiler wait on LDS and vector memory

@@ -34,7 +34,10 @@ struct Layout {
     size_t bw = 0, bwc = 0, spill = 0;
     int64_t spill_words = 0;
     int spill_slots = 0;
-    size_t total = 0;
+    size_t scr = 0, scnt = 0;   // symbolic scratch (after total_min)
+    size_t total_min = 0;       // without the symbolic scratch
+    size_t total = 0;           // with it
+    bool has_scratch = false;   // the caller's workspace holds it
 };
 
 struct BatchHost {
@@ -44,6 +47,7 @@ struct BatchHost {
     std::vector<int32_t> abase, bbase;
     std::vector<int64_t> nnz_tab;
     double avg_a = 1.0, avg_b = 1.0;
+    std::vector<uint64_t> key;  // operands and shapes of the call, verbatim
 };
 
 spgemm_status hip_fail(hipError_t e);
@@ -59,6 +63,7 @@ spgemm_status prepare_batch(int32_t nbatch, const spgemm_csr *A, const spgemm_cs
 spgemm_status run_symbolic(BatchHost &bh, char *ws, int fill, int64_t *nnz_host, hipStream_t s);
 spgemm_status run_numeric(BatchHost &bh, char *ws, hipStream_t s);
 int choose_group(double avg);
+void memo_forget(const void *ws);
 int pow2_group(double avg);
 
 }  // namespace mls

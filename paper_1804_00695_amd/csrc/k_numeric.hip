@@ -160,18 +160,22 @@ __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
                         if (q < pr.y) { jv[d] = bci[q]; bv[d] = bval[q]; }
                     }
                 }
+                // positions first (independent LDS reads), then the adds in step
+                // order; within a step the lanes hold distinct columns of B_k, so
+                // no two lanes add to the same slot and every slot gets its terms
+                // in ascending k. The LDS fp64 add rounds like a plain add.
+                int posv[kNumDepth];
+#pragma unroll
+                for (int d = 0; d < kNumDepth; ++d) posv[d] = jv[d] >= 0 ? pos_lookup(tab, logcap, jv[d]) : -2;
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) {
-                    if (jv[d] >= 0) {
-                        const int pos = pos_lookup(tab, logcap, jv[d]);
-                        if (pos >= 0) acc[pos] = acc[pos] + av[d] * bv[d];
-                        else bad = true;
-                    }
-                    if (u0 + d < n) {   // rows of B longer than G: the rest of this step
+                    if (posv[d] >= 0) atomicAdd(acc + posv[d], av[d] * bv[d]);
+                    else if (posv[d] == -1) bad = true;
+                    if (u0 + d < n && q1v[d] - par[u0 + d].x > G) {   // rows of B longer than G
                         const int q0 = par[u0 + d].x;
                         for (int q = q0 + G + lane; q < q1v[d]; q += G) {
                             const int pos = pos_lookup(tab, logcap, bci[q]);
-                            if (pos >= 0) acc[pos] = acc[pos] + av[d] * bval[q];
+                            if (pos >= 0) atomicAdd(acc + pos, av[d] * bval[q]);
                             else bad = true;
                         }
                     }

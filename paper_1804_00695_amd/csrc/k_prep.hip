@@ -41,12 +41,9 @@ __device__ __forceinline__ uint32_t group_ballot(bool pred, int slot_in_wave)
 // CSR checks over the A rows (which = 0) or B rows (which = 1) of a batch:
 // row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, columns in range and
 // strictly increasing. Column indices outside [0, nnz) are never read.
-__global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
+__device__ __forceinline__ bool validate_row(const Batch &b, int which, const int64_t *nnz_tab, int g)
 {
-    const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
-    const int g = blockIdx.x * kRowsPerWG + slot;
-    const int total = which == 0 ? b.na : b.nb;
-    if (g >= total) return;   // whole row groups leave together (g is uniform per group)
+    const int lane = threadIdx.x % kRowG;
     const int32_t *base = which == 0 ? b.abase : b.bbase;
     const int t = b.nprob == 1 ? 0 : find_prob(base, b.nprob, g);
     const Prob P = get_prob(b, t);
@@ -74,7 +71,22 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
             carry = __shfl(c, kRowG - 1, kRowG);
         }
     }
-    if (bad) atomicOr(err, kErrBadCsr);
+    return bad;
+}
+
+constexpr int kLoopRowsPerWG = 256;   // rows per workgroup of the helper kernels
+
+__global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
+{
+    const int slot = threadIdx.x / kRowG;
+    const int total = which == 0 ? b.na : b.nb;
+    bool bad_any = false;
+    for (int r = slot; r < kLoopRowsPerWG; r += kRowsPerWG) {
+        const int g = blockIdx.x * kLoopRowsPerWG + r;
+        if (g >= total) break;   // uniform per row group
+        bad_any |= validate_row(b, which, nnz_tab, g);
+    }
+    if (bad_any) atomicOr(err, kErrBadCsr);
 }
 
 // Column compression of every B row (set = col >> 5, mask bit = col & 31),
@@ -82,13 +94,10 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
 // Chunks of 32 entries: a lane starts a word where its set differs from the
 // previous entry's; masks are OR-ed in LDS; the last word of a chunk stays
 // open (it may continue in the next chunk).
-__global__ __launch_bounds__(kWG) void k_compress(Batch b)
+__device__ __forceinline__ void compress_row(const Batch &b, int g, uint32_t *wset, uint32_t *wmsk)
 {
-    __shared__ uint32_t s_set[kRowsPerWG][kRowG + 1];
-    __shared__ uint32_t s_msk[kRowsPerWG][kRowG + 1];
     const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
     const int wslot = slot & 1;   // which half of the 64-lane wave
-    const int g = blockIdx.x * kRowsPerWG + slot;
     const bool row_ok = g < b.nb;
     int t = 0, k = 0;
     Prob P = b.p0;
@@ -101,9 +110,9 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
     const int e = row_ok ? gp(P.brp)[k + 1] - P.b_off : 0;
     const MLS_G int32_t *__restrict__ bci = gp(P.bci);
     MLS_G u32x2 *__restrict__ out = (MLS_G u32x2 *)P.bw + s;
-    uint32_t *wset = s_set[slot], *wmsk = s_msk[slot];
     const uint32_t kNone = 0xffffffffu;
     uint32_t carry_set = kNone, carry_msk = 0;
+    (void)slot;
     int nout = 0;
     // every group of the wave runs the same number of chunks (shuffles need all lanes)
     int len = e - s;
@@ -166,6 +175,19 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
     }
 }
 
+__global__ __launch_bounds__(kWG) void k_compress(Batch b)
+{
+    __shared__ uint32_t s_set[kRowsPerWG][kRowG + 1];
+    __shared__ uint32_t s_msk[kRowsPerWG][kRowG + 1];
+    const int slot = threadIdx.x / kRowG;
+    // both row groups of a wave run the same rows count (they share ballots)
+    for (int r = slot & ~1; r < kLoopRowsPerWG; r += kRowsPerWG) {
+        const int g0 = blockIdx.x * kLoopRowsPerWG + r;
+        if (g0 >= b.nb) break;   // uniform per wave
+        compress_row(b, g0 + (slot & 1), s_set[slot], s_msk[slot]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row sizes and bins.
 //   kModeCount  : size = sum over in-range k of the word count of B_k (an
@@ -199,6 +221,22 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
     if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) tsum = 0;
     __syncthreads();
+    if (mode == kModeNumeric) {   // size = nnz(C_i): one thread per row
+        const int g = blockIdx.x * kBinRowsPerWG + threadIdx.x;
+        if (g < b.na) {
+            const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+            const Prob P = get_prob(b, t);
+            const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+            const int nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
+            const int c = class_of(mode, nc, force_spill);
+            gpw(sc.val)[g] = nc;
+            gpw(sc.cls)[g] = (uint8_t)c;
+            atomicAdd(&cnt[c], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(sc.bin_count + threadIdx.x, cnt[threadIdx.x]);
+        return;
+    }
     const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
     for (int r = slot; r < kBinRowsPerWG; r += kRowsPerWG) {
         const int g = blockIdx.x * kBinRowsPerWG + r;
@@ -231,8 +269,12 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
                 c = kBinEmpty;
                 if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
                 atomicAdd(&tsum, (unsigned long long)size);
+            } else if (mode == kModeFill && sc.scr && gp(sc.scnt)[g] >= 0) {
+                c = kBinEmpty;   // expanded from the count pass's scratch words
             } else {
                 c = class_of(mode, size, force_spill);
+                // rows without work get no symbolic kernel: their scratch is empty
+                if (mode == kModeCount && sc.scr && c == kBinEmpty) gpw(sc.scnt)[g] = 0;
             }
             if (size >= 0x7fffffffLL) size = 0x7fffffff;
             gpw(sc.val)[g] = (int32_t)size;
@@ -390,14 +432,14 @@ void launch_validate(const Batch &b, int which, const int64_t *nnz_tab, uint32_t
     int n = which == 0 ? b.na : b.nb;
     if (n <= 0) return;
     ProfScope ps("validate", s);
-    hipLaunchKernelGGL(k_validate, dim3(nblk(n, kRowsPerWG)), dim3(kWG), 0, s, b, which, nnz_tab, err);
+    hipLaunchKernelGGL(k_validate, dim3(nblk(n, kLoopRowsPerWG)), dim3(kWG), 0, s, b, which, nnz_tab, err);
 }
 
 void launch_compress(const Batch &b, hipStream_t s)
 {
     if (b.nb <= 0) return;
     ProfScope ps("compress", s);
-    hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kRowsPerWG)), dim3(kWG), 0, s, b);
+    hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kLoopRowsPerWG)), dim3(kWG), 0, s, b);
 }
 
 void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsigned long long *total,

@@ -59,8 +59,8 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
     constexpr int ROWB = FILL ? CAP * 12 : CAP * 8;
     constexpr int NW = nw_for(ROWB, W);
     constexpr int LIST = FILL ? CAP / 2 : 1;
-    __shared__ uint32_t s_key[NW * W * CAP];
-    __shared__ uint32_t s_msk[NW * W * CAP];
+    __shared__ __attribute__((aligned(16))) uint32_t s_key[NW * W * CAP];
+    __shared__ __attribute__((aligned(16))) uint32_t s_msk[NW * W * CAP];
     __shared__ uint2 s_list[NW * W * LIST];
     __shared__ int s_cnt[NW * W];
 
@@ -92,7 +92,16 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
         int logcap = ilog2_ceil(FILL ? 2 * size : size);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
-        for (int h = lane; h < cap; h += G) { key[h] = kEmptyKey; msk[h] = 0u; }
+        // table passes touch 4 slots per lane per access when the table is large enough
+        const bool vec = cap >= 4 * G;
+        if (vec) {
+            for (int h = 4 * lane; h < cap; h += 4 * G) {
+                *(uint4 *)(key + h) = make_uint4(kEmptyKey, kEmptyKey, kEmptyKey, kEmptyKey);
+                *(uint4 *)(msk + h) = make_uint4(0u, 0u, 0u, 0u);
+            }
+        } else {
+            for (int h = lane; h < cap; h += G) { key[h] = kEmptyKey; msk[h] = 0u; }
+        }
         if (lane == 0) s_cnt[rs] = 0;
         wave_sync();
         if (active) {
@@ -121,10 +130,66 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
         }
         wave_sync();
         if (!FILL) {
-            int c = 0;
-            for (int h = lane; h < cap; h += G) c += __popc(msk[h]);
+            // popcount of the union and number of occupied slots; each lane owns
+            // 4 (vec) or 1 consecutive slots per pass
+            const int per = vec ? 4 : 1;
+            int c = 0, nsets = 0;
+            for (int h = per * lane; h < cap; h += per * G) {
+                if (vec) {
+                    const uint4 k4 = *(const uint4 *)(key + h);
+                    const uint4 m4 = *(const uint4 *)(msk + h);
+                    c += __popc(m4.x) + __popc(m4.y) + __popc(m4.z) + __popc(m4.w);
+                    nsets += (k4.x != kEmptyKey) + (k4.y != kEmptyKey) + (k4.z != kEmptyKey) + (k4.w != kEmptyKey);
+                } else {
+                    c += __popc(msk[h]);
+                    nsets += key[h] != kEmptyKey;
+                }
+            }
             c = group_sum<G>(c);
+            nsets = group_sum<G>(nsets);
             if (active && lane == 0) val[g] = c;
+            if (sc.scr) {
+                // keep the row's words for the fill pass (compacted in slot order)
+                const bool fits = nsets <= kScratchWords;
+                if (active && lane == 0) gpw(sc.scnt)[g] = fits ? nsets : -1;
+                if (fits) {
+                    MLS_G u32x2 *dst = (MLS_G u32x2 *)sc.scr + (int64_t)g * kScratchWords;
+                    int base = 0;
+                    for (int h0 = 0; h0 < cap; h0 += per * G) {
+                        const int h = h0 + per * lane;
+                        uint32_t kk[4], mm[4];
+                        int nl = 0;
+                        if (h < cap) {
+                            if (vec) {
+                                const uint4 k4 = *(const uint4 *)(key + h);
+                                const uint4 m4 = *(const uint4 *)(msk + h);
+                                kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
+                                mm[0] = m4.x; mm[1] = m4.y; mm[2] = m4.z; mm[3] = m4.w;
+                            } else {
+                                kk[0] = key[h]; mm[0] = msk[h];
+                            }
+                            for (int x = 0; x < per; ++x) nl += kk[x] != kEmptyKey;
+                        }
+                        // exclusive prefix of nl over the group
+                        int incl = nl;
+#pragma unroll
+                        for (int o = 1; o < G; o <<= 1) {
+                            const int y = __shfl_up(incl, o, G);
+                            if (lane >= o) incl += y;
+                        }
+                        const int tot = __shfl(incl, G - 1, G);
+                        if (active && nl) {
+                            int w = base + incl - nl;
+                            for (int x = 0; x < per; ++x)
+                                if (kk[x] != kEmptyKey) {
+                                    u32x2 v; v.x = kk[x]; v.y = mm[x];
+                                    dst[w++] = v;
+                                }
+                        }
+                        base += tot;
+                    }
+                }
+            }
         } else {
             for (int h = lane; h < cap; h += G) {
                 uint32_t k = key[h];
@@ -207,6 +272,7 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
                 int s = 0;
                 for (int x = 0; x < kWG / kWave; ++x) s += s_red[x];
                 gpw(sc.val)[g] = s;
+                if (sc.scr) gpw(sc.scnt)[g] = -1;   // recomputed by the fill pass
             }
             __syncthreads();
         } else {
@@ -249,6 +315,75 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
         }
         __syncthreads();
     }
+}
+
+// Fill pass from the count pass's scratch: G lanes per row load the row's
+// words, place each word at the popcount sum of the words with smaller sets
+// and expand its bits into ascending columns. Rows without scratch words
+// (scnt < 0) are left to the recomputing fill kernels.
+template <int G>
+__global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = kWG / kWave;
+    __shared__ uint2 s_list[NW * W * kScratchWords];
+    const int wave = threadIdx.x >> 6;
+    const int lw = threadIdx.x & 63;
+    const int slot = lw / G, lane = lw % G;
+    const int rs = wave * W + slot;
+    uint2 *list = s_list + rs * kScratchWords;
+    const int rows_per_wg = NW * W;
+    for (int g0 = blockIdx.x * rows_per_wg; g0 < b.na; g0 += gridDim.x * rows_per_wg) {
+        const int g = g0 + rs;
+        const bool row_ok = g < b.na;
+        const int n = row_ok ? gp(sc.scnt)[g] : -1;
+        if (n > 0) {
+            const MLS_G u32x2 *src = (const MLS_G u32x2 *)sc.scr + (int64_t)g * kScratchWords;
+            for (int e = lane; e < n; e += G) {
+                u32x2 w = src[e];
+                list[e] = make_uint2(w.x, w.y);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (n > 0) {
+            const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+            const Prob P = get_prob(b, t);
+            const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+            const int cs = gp(P.crp)[i] - P.c_off;
+            const int ce = gp(P.crp)[i + 1] - P.c_off;
+            MLS_G int32_t *__restrict__ cci = gpw(P.cci);
+            for (int e = lane; e < n; e += G) {
+                const uint2 me = list[e];
+                int off = 0;
+                for (int f = 0; f < n; ++f) {
+                    const uint2 o = list[f];
+                    off += (o.x < me.x) ? __popc(o.y) : 0;
+                }
+                uint32_t m = me.y;
+                int pos = cs + off;
+                while (m) {
+                    const int bit = __ffs(m) - 1;
+                    if (pos < ce) cci[pos] = (int32_t)(me.x * 32u + (uint32_t)bit);
+                    else atomicOr(sc.err, kErrStructure);
+                    ++pos;
+                    m &= m - 1u;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
+void launch_sym_expand(const Batch &b, const Sched &sc, hipStream_t s)
+{
+    if (b.na <= 0 || !sc.scr) return;
+    static int cus = device_cu_count();
+    ProfScope ps("sym_expand_G32", s);
+    hipLaunchKernelGGL(k_sym_expand<32>, dim3(cus * 8), dim3(kWG), 0, s, b, sc);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,6 +26,9 @@ void launch_write_rowptr(const Batch &b, const int64_t *prefix, int64_t *totals,
 void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, uint32_t *spill_bitmaps,
                      int spill_slots, int64_t spill_words, hipStream_t s);
 
+// Fill pass from the count pass's scratch words (rows with scnt >= 0).
+void launch_sym_expand(const Batch &b, const Sched &sc, hipStream_t s);
+
 // Numeric phase (row-range fused multiply-add) over the binned rows.
 void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s);
 

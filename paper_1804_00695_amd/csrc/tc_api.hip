@@ -67,7 +67,7 @@ spgemm_status spgemm_tc_lower(const spgemm_csr *G, int32_t *perm, int32_t *lrp, 
 spgemm_status spgemm_tc_workspace_size(const spgemm_csr *L, size_t *bytes)
 {
     if (!L || !bytes) return SPGEMM_ERR_INVALID_ARG;
-    *bytes = make_layout(1, L->nrows, L->nrows, L->nnz, L->ncols, true).total;
+    *bytes = make_layout(1, L->nrows, L->nrows, L->nnz, L->ncols, true).total_min;
     return SPGEMM_OK;
 }
 
@@ -78,6 +78,7 @@ spgemm_status spgemm_tc(const spgemm_csr *L, int64_t *counts, int64_t *total_hos
     if (L->nrows != L->ncols) return SPGEMM_ERR_DIM_MISMATCH;
     spgemm_csr Lp = *L;
     Lp.values = nullptr;
+    memo_forget(ws_v);
     BatchHost bh;
     spgemm_status st = prepare_batch(1, &Lp, &Lp, nullptr, false, true, (char *)ws_v, ws_bytes, s, bh);
     if (st != SPGEMM_OK) return st;

@@ -178,3 +178,46 @@ def test_deterministic_repeat():
     r2 = gpu_product(A, A)
     for x, y in zip(r1, r2):
         assert np.array_equal(x, y)
+
+
+def raw_symbolic(A, B, ws_bytes_fn=lambda full, minimal: full, separate_fill_ws=False, fill_twice=False):
+    """Count and fill through the ABI with chosen workspaces."""
+    import ctypes
+    dA, dB = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B)
+    full = mls.workspace_size(dA, dB)
+    nb = ws_bytes_fn(full, None)
+    w1 = mls.Workspace()
+    w2 = mls.Workspace()
+    p1 = w1.get(nb)
+    crp = torch.empty(A.nrows + 1, dtype=torch.int32, device="cuda")
+    nnz = ctypes.c_int64(0)
+    ha, hb = dA.handle(), dB.handle()
+    s = mls.stream_handle()
+    mls.check(mls.lib.spgemm_symbolic(ctypes.byref(ha), ctypes.byref(hb), crp.data_ptr(), None, ctypes.byref(nnz),
+                                      p1, nb, s), "count")
+    cci = torch.full((max(nnz.value, 1),), -7, dtype=torch.int32, device="cuda")
+    p2 = w2.get(nb) if separate_fill_ws else p1
+    for _ in range(2 if fill_twice else 1):
+        mls.check(mls.lib.spgemm_symbolic(ctypes.byref(ha), ctypes.byref(hb), crp.data_ptr(), cci.data_ptr(), None,
+                                          p2, nb, s), "fill")
+    torch.cuda.synchronize()
+    mls.check(mls.lib.spgemm_check_errors(p2, nb, s), "errors")
+    return crp.cpu().numpy(), cci[:nnz.value].cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", ["scratch", "separate_ws", "no_scratch_room", "fill_twice"])
+def test_symbolic_fill_paths(mode):
+    A = synth.stencil27_3d(9, amp=0.1)
+    B = wide_rows(300, 729, 60, 5)          # rows of C with > 64 words overflow the scratch
+    for X, Y in ((A, A), (synth.poisson_csr(400, 729, 20.0, 3), B)):
+        R, _ = oracle.spgemm(X, Y, with_abs=False)
+        kw = {}
+        if mode == "separate_ws":
+            kw["separate_fill_ws"] = True
+        elif mode == "no_scratch_room":
+            # one byte short of the full size: above the minimum, without the scratch
+            kw["ws_bytes_fn"] = lambda full, _: full - 1
+        elif mode == "fill_twice":
+            kw["fill_twice"] = True
+        rp, ci = raw_symbolic(X, Y, **kw)
+        assert np.array_equal(rp, R.row_ptr) and np.array_equal(ci, R.col_idx)
