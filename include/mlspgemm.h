@@ -78,7 +78,9 @@ typedef enum {
     SPGEMM_OPT_FORCE_SPILL = 1,   /* 1: every row takes the global-memory accumulator path (test knob) */
     SPGEMM_OPT_GROUP_SIZE = 2,    /* 0 (default): lanes per row chosen from row lengths; else 8/16/32/64 */
     SPGEMM_OPT_UNROLL = 3,        /* reserved */
-    SPGEMM_OPT_PROFILE = 4        /* 1: time every kernel launch with a HIP event pair on its stream */
+    SPGEMM_OPT_PROFILE = 4,       /* 1: time every kernel launch with a HIP event pair on its stream */
+    SPGEMM_OPT_WIDE_TABLE = 5     /* 1: the numeric phase keeps 8-byte (column, position) hash slots
+                                     even where column and position fit one 32-bit slot (test knob) */
 } spgemm_option;
 spgemm_status spgemm_set_option(spgemm_option opt, int64_t value);
 int64_t spgemm_get_option(spgemm_option opt);

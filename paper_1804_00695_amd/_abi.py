@@ -77,7 +77,7 @@ SIGNATURES = {
     "spgemm_mask_gather": (ctypes.c_int, [CSRP, CSRP, P, P]),
 }
 
-OPT_VALIDATE, OPT_FORCE_SPILL, OPT_GROUP_SIZE, OPT_PROFILE = 0, 1, 2, 4
+OPT_VALIDATE, OPT_FORCE_SPILL, OPT_GROUP_SIZE, OPT_PROFILE, OPT_WIDE_TABLE = 0, 1, 2, 4, 5
 STATUS_NAMES = ["OK", "INVALID_ARG", "BAD_CSR", "DIM_MISMATCH", "INDEX_OVERFLOW", "WORKSPACE_TOO_SMALL",
                 "BUDGET", "HIP", "UNSUPPORTED", "STRUCTURE"]
 

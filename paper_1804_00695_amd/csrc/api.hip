@@ -192,6 +192,9 @@ spgemm_status prepare_batch(int32_t nbatch, const spgemm_csr *A, const spgemm_cs
     bt.nprob = nbatch;
     bt.na = (int32_t)na;
     bt.nb = (int32_t)nb;
+    // 0 keeps the numeric phase on the wide hash slots
+    if (!g_opt.wide_table)
+        for (int t = 0; t < nbatch; ++t) bt.max_ncols = std::max(bt.max_ncols, B[t].ncols);
     bt.p0 = out.probs[0];
     bt.probs = (const Prob *)(ws + out.layout.probs);
     bt.abase = (const int32_t *)(ws + out.layout.abase);
@@ -252,7 +255,14 @@ spgemm_status run_symbolic(BatchHost &bh, char *ws, int fill, int64_t *nnz_host,
     reset_header(ws, L, s);
     if (!fill && g_opt.validate) {
         launch_validate(bh.batch, 0, (const int64_t *)(ws + L.nnz_tab), sc.err, s);
-        launch_validate(bh.batch, 1, (const int64_t *)(ws + L.nnz_tab), sc.err, s);
+        // B is checked by the same rules as A: skip it when every B_t is A_t itself
+        bool same = true;
+        for (int t = 0; t < bh.batch.nprob && same; ++t) {
+            const Prob &q = bh.probs[t];
+            same = q.arp == q.brp && q.aci == q.bci && q.nrows == q.krows && q.ncols == q.krows &&
+                   q.a_off == q.b_off && bh.nnz_tab[2 * t] == bh.nnz_tab[2 * t + 1];
+        }
+        if (!same) launch_validate(bh.batch, 1, (const int64_t *)(ws + L.nnz_tab), sc.err, s);
         spgemm_status st = check_launch();
         if (st != SPGEMM_OK) return st;
         st = read_errors(ws, L, s);
@@ -349,6 +359,7 @@ spgemm_status spgemm_set_option(spgemm_option opt, int64_t value)
         return SPGEMM_OK;
     case SPGEMM_OPT_UNROLL: return SPGEMM_OK;
     case SPGEMM_OPT_PROFILE: g_opt.profile = value != 0; return SPGEMM_OK;
+    case SPGEMM_OPT_WIDE_TABLE: g_opt.wide_table = value != 0; return SPGEMM_OK;
     }
     return SPGEMM_ERR_INVALID_ARG;
 }
@@ -360,6 +371,7 @@ int64_t spgemm_get_option(spgemm_option opt)
     case SPGEMM_OPT_FORCE_SPILL: return g_opt.force_spill;
     case SPGEMM_OPT_GROUP_SIZE: return g_opt.group_size;
     case SPGEMM_OPT_PROFILE: return g_opt.profile;
+    case SPGEMM_OPT_WIDE_TABLE: return g_opt.wide_table;
     default: return 0;
     }
 }

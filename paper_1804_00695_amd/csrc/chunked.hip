@@ -222,6 +222,7 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
             std::memset(&bt, 0, sizeof(bt));
             bt.nprob = 1;
             bt.na = a.r1 - a.r0;
+            bt.max_ncols = g_opt.wide_table ? 0 : B->ncols;
             Prob &q = bt.p0;
             q.arp = a.arp; q.aci = a.aci; q.aval = a.aval;
             q.brp = bq.brp; q.bci = bq.bci; q.bval = bq.bval;

@@ -69,7 +69,7 @@ struct Batch {
     int32_t nprob;
     int32_t na;             // total A rows
     int32_t nb;             // total B rows
-    int32_t pad;
+    int32_t max_ncols;      // largest column count of C over the products (0 = unknown)
 };
 
 // Per-phase device state inside the workspace.
@@ -163,37 +163,54 @@ __device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
 
 // Per-wave task schedule. Tasks of a bin are split into one contiguous slab
 // per XCD (workgroup w runs on XCD w % 8, and the CUs of an XCD share one L2).
-// Inside a slab the waves of that XCD take tasks round-robin, so at any time
-// the rows in flight on an XCD form a narrow window of consecutive tasks:
-// neighbouring rows share most of their rows of B, and a narrow window keeps
-// that shared working set inside the L2. No atomics are involved.
+// Inside a slab, waves take blocks of kTaskBlock tasks from a per-XCD counter;
+// block b holds the tasks base + c, base + c + S, ..., c = b mod S, base set
+// by b div S, with S the number of waves the grid places on the XCD. While
+// every wave is busy, the rows in flight on an XCD therefore form a narrow
+// window of about S consecutive tasks (neighbouring rows share most of their
+// rows of B, and a narrow window keeps that shared working set in the L2),
+// and workgroups that become resident late, or never, leave no tasks behind.
+constexpr int kTaskBlock = 8;
+
 struct TaskIter {
-    int next, hi, stride;
+    int lo, hi, S, cur, left;
 };
 
 __device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg)
 {
     const int x = (int)(blockIdx.x % kXcd);
-    const int lo = (int)(((int64_t)ntasks * x) / kXcd);
-    const int hi = (int)(((int64_t)ntasks * (x + 1)) / kXcd);
-    const int wgs_x = ((int)gridDim.x - x + kXcd - 1) / kXcd;   // workgroups on this XCD
-    const int wave = (int)(threadIdx.x >> 6);
     TaskIter it;
-    it.next = lo + (int)(blockIdx.x / kXcd) * waves_per_wg + wave;
-    it.hi = hi;
-    it.stride = wgs_x * waves_per_wg;
+    it.lo = (int)(((int64_t)ntasks * x) / kXcd);
+    it.hi = (int)(((int64_t)ntasks * (x + 1)) / kXcd);
+    const int wgs_x = ((int)gridDim.x - x + kXcd - 1) / kXcd;   // workgroups on this XCD
+    it.S = wgs_x * waves_per_wg;
+    if (it.S < 1) it.S = 1;
+    it.cur = 0;
+    it.left = 0;
     return it;
 }
 
-// Next task of this wave, or -1. Uniform across the wave.
+// Next task of this wave, or -1. Uniform across the wave; call with all lanes
+// active. cursor: the bin's kXcd counters, zero before the launch.
 __device__ __forceinline__ int next_task_wave(int32_t *cursor, int ntasks, TaskIter &it)
 {
-    (void)cursor;
     (void)ntasks;
-    if (it.next >= it.hi) return -1;
-    const int t = it.next;
-    it.next += it.stride;
-    return t;
+    for (;;) {
+        if (it.left > 0) {
+            const int t = it.cur;
+            it.cur += it.S;
+            --it.left;
+            if (t < it.hi) return t;
+            it.left = 0;
+        }
+        int blk = 0;
+        if ((threadIdx.x & 63) == 0) blk = atomicAdd(cursor + blockIdx.x % kXcd, 1);
+        blk = __builtin_amdgcn_readlane(blk, 0);
+        const int64_t base = (int64_t)it.lo + (int64_t)(blk / it.S) * it.S * kTaskBlock + blk % it.S;
+        if (base >= it.hi) return -1;
+        it.cur = (int)base;
+        it.left = kTaskBlock;
+    }
 }
 
 }  // namespace mls

@@ -14,6 +14,7 @@ namespace mls {
 struct Options {
     bool validate = true;
     bool force_spill = false;
+    bool wide_table = false;
     int64_t group_size = 0;
     bool profile = false;
 };

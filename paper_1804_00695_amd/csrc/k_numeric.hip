@@ -6,7 +6,8 @@
 //
 // LDS path: G lanes own a row of C. Its (sorted) columns are loaded once into
 // an LDS hash mapping column -> position in the row, next to an LDS array of
-// fp64 accumulators in row order. The entries of row i of A are taken in
+// fp64 accumulators in row order. When C has few enough columns, a table slot
+// packs column and position into one 32-bit word. The entries of row i of A are taken in
 // stored order; for each, the G lanes take distinct entries of B_k, so no two
 // lanes of a step touch the same accumulator and every c_ij receives its
 // terms in ascending k -- the order of the row-wise formulation. Products are
@@ -26,7 +27,7 @@
 
 namespace mls {
 
-constexpr int kNumDepth = 8;   // steps whose B loads are issued together
+constexpr int kNumDepth = 4;   // steps whose B loads are issued together
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -42,36 +43,130 @@ constexpr int nw_num(int row_bytes, int rows_per_wave)
     return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
 }
 
-__device__ __forceinline__ int pos_lookup(const int2 *tab, int logcap, int j)
-{
-    const uint32_t cmask = (1u << logcap) - 1u;
-    uint32_t h = hslot((uint32_t)j, logcap);
-    for (uint32_t probe = 0; probe <= cmask; ++probe) {
-        int2 v = tab[h];
-        if (v.x == j) return v.y;
-        if (v.x == -1) return -1;
-        h = (h + 1u) & cmask;
+// Column -> position table of one row of C, in one of two layouts:
+//   wide  : int2 slots (column, position), any column count;
+//   packed: one uint32 per slot, column << PB | position, with PB bits for the
+//           position (positions < CAP/2). Usable when every column index of C
+//           fits in the remaining bits; halves the bytes of every lookup.
+// Empty slots hold -1 (all ones); a packed key never equals it because the
+// column range excludes the all-ones column field.
+template <int CAP>
+struct PackBits {
+    static constexpr int PB = (CAP == 256) ? 7 : (CAP == 1024 ? 9 : 11);
+    static_assert(CAP == 256 || CAP == 1024 || CAP == 4096, "table class");
+    static constexpr uint32_t kMaxCols = (1u << (32 - PB)) - 1u;   // columns < this fit
+};
+
+template <int CAP, bool PACK>
+struct PosTab {
+    uint32_t *t;   // CAP words (packed) or 2*CAP words (wide)
+
+    __device__ __forceinline__ void clear(int cap, int lane, int G)
+    {
+        if (PACK) {
+            if (cap >= 4 * G) {
+                for (int h = 4 * lane; h < cap; h += 4 * G)
+                    *(uint4 *)(t + h) = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+            } else {
+                for (int h = lane; h < cap; h += G) t[h] = 0xffffffffu;
+            }
+        } else {
+            for (int h = lane; h < cap; h += G) ((int2 *)t)[h] = make_int2(-1, 0);
+        }
     }
-    return -1;
+
+    __device__ __forceinline__ void insert(int logcap, int j, int pos)
+    {
+        const uint32_t cmask = (1u << logcap) - 1u;
+        uint32_t h = hslot((uint32_t)j, logcap);
+        if (PACK) {
+            const uint32_t v = ((uint32_t)j << PackBits<CAP>::PB) | (uint32_t)pos;
+            for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                if (atomicCAS(t + h, 0xffffffffu, v) == 0xffffffffu) return;
+                h = (h + 1u) & cmask;
+            }
+        } else {
+            int2 *tab = (int2 *)t;
+            for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                int old = atomicCAS(&tab[h].x, -1, j);
+                if (old == -1) { tab[h].y = pos; return; }
+                h = (h + 1u) & cmask;
+            }
+        }
+    }
+
+    // position of column j in the row, or -1 when j is not in the row
+    __device__ __forceinline__ int lookup(int logcap, int j) const
+    {
+        const uint32_t cmask = (1u << logcap) - 1u;
+        uint32_t h = hslot((uint32_t)j, logcap);
+        if (PACK) {
+            constexpr int PB = PackBits<CAP>::PB;
+            for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                const uint32_t v = t[h];
+                if ((v >> PB) == (uint32_t)j) return (int)(v & ((1u << PB) - 1u));
+                if (v == 0xffffffffu) return -1;
+                h = (h + 1u) & cmask;
+            }
+        } else {
+            const int2 *tab = (const int2 *)t;
+            for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                const int2 v = tab[h];
+                if (v.x == j) return v.y;
+                if (v.x == -1) return -1;
+                h = (h + 1u) & cmask;
+            }
+        }
+        return -1;
+    }
+};
+
+constexpr int num_row_bytes(int CAP, int G, bool PACK)
+{
+    return CAP * (PACK ? 4 : 8) + (CAP / 2) * 8 + G * 16;
 }
 
-__device__ __forceinline__ void pos_insert(int2 *tab, int logcap, int j, int pos)
+// Where a row of the bin lives: product t, local row i, output size nc, the
+// start of its C entries (cs) and its A entry range [ps, pe), all local.
+struct RowMeta {
+    int t, nc, cs, ps, pe;
+    bool active;
+};
+
+// The descriptor of product t: the kernel argument for a single product (its
+// fields then live in scalar registers), else the batch's descriptor array.
+template <bool MULTI>
+__device__ __forceinline__ Prob prob_of(const Batch &b, int t)
 {
-    const uint32_t cmask = (1u << logcap) - 1u;
-    uint32_t h = hslot((uint32_t)j, logcap);
-    for (uint32_t probe = 0; probe <= cmask; ++probe) {
-        int old = atomicCAS(&tab[h].x, -1, j);
-        if (old == -1) { tab[h].y = pos; return; }
-        h = (h + 1u) & cmask;
-    }
+    if (!MULTI) return b.p0;
+    return get_prob(b, t);
 }
 
-template <int G, int CAP>
-__global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
+template <bool MULTI>
+__device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, bool active, int g)
+{
+    RowMeta m{0, 0, 0, 0, 0, active};
+    if (!active) return m;
+    int i = g;
+    if (MULTI) {
+        m.t = find_prob(b.abase, b.nprob, g);
+        i = g - gp(b.abase)[m.t];
+    }
+    const Prob P = prob_of<MULTI>(b, m.t);
+    m.nc = gp(sc.val)[g];
+    m.cs = gp(P.crp)[i] - P.c_off;
+    m.ps = gp(P.arp)[i] - P.a_off;
+    m.pe = gp(P.arp)[i + 1] - P.a_off;
+    return m;
+}
+
+template <int G, int CAP, bool PACK, bool MULTI>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 : 8))) void k_num_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_num(CAP * 12 + G * 16, W);
-    __shared__ int2 s_tab[NW * W * CAP];
+    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK), W);
+    constexpr int TW = PACK ? CAP : 2 * CAP;   // table words per row
+    __shared__ __attribute__((aligned(16))) uint32_t s_tab[NW * W * TW];
     __shared__ double s_acc[NW * W * (CAP / 2)];
     __shared__ int4 s_par[NW * W * G];   // staged entries of row i of A: (q0, q1, a)
 
@@ -80,31 +175,34 @@ __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
     const int lw = threadIdx.x & 63;
     const int slot = lw / G, lane = lw % G;
     const int rs = wave * W + slot;
-    int2 *tab = s_tab + rs * CAP;
+    PosTab<CAP, PACK> tab{s_tab + rs * TW};
     double *acc = s_acc + rs * (CAP / 2);
     int4 *par = s_par + rs * G;
 
     const MLS_G int32_t *perm = gp(sc.perm);
-    const MLS_G int32_t *val = gp(sc.val);
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
     TaskIter it = task_iter(ntasks, NW);
-    for (;;) {
-        int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        if (task < 0) break;
-        const int r = task * W + slot;
-        const bool active = r < n_bin;
-        int g = active ? perm[start + r] : 0;
-        int t = (!active || b.nprob == 1) ? 0 : find_prob(b.abase, b.nprob, g);
-        const Prob P = get_prob(b, t);
-        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
-        const int nc = active ? val[g] : 0;
+    // Rows are software-pipelined: the next row's perm entry is loaded when a
+    // row starts and its metadata (size, row pointers) in the middle of the
+    // row, so a row starts with its dependent index loads already done.
+    int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+    int g_cur = 0;
+    if (task >= 0 && task * W + slot < n_bin) g_cur = perm[start + task * W + slot];
+    RowMeta m = row_meta<MULTI>(b, sc, task >= 0 && task * W + slot < n_bin, g_cur);
+    while (task >= 0) {
+        const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+        const bool act_n = task_n >= 0 && task_n * W + slot < n_bin;
+        const int g_n = act_n ? perm[start + task_n * W + slot] : 0;
+
+        const bool active = m.active;
+        const Prob P = prob_of<MULTI>(b, m.t);
+        const int nc = m.nc;
         int logcap = ilog2_ceil(2 * nc);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
-        for (int h = lane; h < cap; h += G) tab[h] = make_int2(-1, 0);
-        nwave_sync();
+        tab.clear(cap, lane, G);
         // descriptor fields into registers once per row, as global pointers
         const MLS_G int32_t *__restrict__ aci = gp(P.aci);
         const MLS_G double *__restrict__ aval = gp(P.aval);
@@ -113,51 +211,50 @@ __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
         const MLS_G double *__restrict__ bval = gp(P.bval);
         const MLS_G int32_t *__restrict__ cci = gp(P.cci);
         MLS_G double *__restrict__ cval = gpw(P.cval);
-        const int a_off = P.a_off, b_off = P.b_off, k_lo = P.k_lo, k_hi = P.k_hi;
+        const int b_off = P.b_off, k_lo = P.k_lo, k_hi = P.k_hi;
         const bool accumulate = P.accumulate != 0;
-        int cs = 0, ps = 0, pe = 0;
-        if (active) {
-            cs = gp(P.crp)[i] - P.c_off;
-            ps = gp(P.arp)[i] - a_off;
-            pe = gp(P.arp)[i + 1] - a_off;
-            for (int e = lane; e < nc; e += G) {
-                pos_insert(tab, logcap, cci[cs + e], e);
-                acc[e] = accumulate ? cval[cs + e] : 0.0;
-            }
+        const int cs = m.cs, ps = m.ps, pe = m.pe;
+        // the first chunk of row i of A is loaded before C's columns are hashed
+        int ka = -1;
+        double sa = 0.0;
+        if (ps + lane < pe) { ka = aci[ps + lane]; sa = aval[ps + lane]; }
+        nwave_sync();
+        for (int e = lane; e < nc; e += G) {
+            tab.insert(logcap, cci[cs + e], e);
+            acc[e] = accumulate ? cval[cs + e] : 0.0;
         }
+        m = row_meta<MULTI>(b, sc, act_n, g_n);
         nwave_sync();
         bool bad = false;
         for (int pc = ps; pc < pe; pc += G) {
-            // stage a chunk of row i of A: one round of loads for G entries
-            {
-                const int p = pc + lane;
-                int q0 = 0, q1 = 0;
-                double a = 0.0;
-                if (p < pe) {
-                    const int k = aci[p];
-                    a = aval[p];
-                    if (k >= k_lo && k < k_hi) {
-                        q0 = brp[k - k_lo] - b_off;
-                        q1 = brp[k - k_lo + 1] - b_off;
-                    }
-                }
-                par[lane] = make_int4(q0, q1, __double2loint(a), __double2hiint(a));
+            // stage the chunk: (q0, q1, a) of entry pc + lane
+            int sq0 = 0, sq1 = 0;
+            if (ka >= k_lo && ka < k_hi) {
+                sq0 = brp[ka - k_lo] - b_off;
+                sq1 = brp[ka - k_lo + 1] - b_off;
             }
+            par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
             nwave_sync();
+            // the next chunk's entries of A are in flight during this chunk's steps
+            ka = -1;
+            sa = 0.0;
+            if (pc + G + lane < pe) { ka = aci[pc + G + lane]; sa = aval[pc + G + lane]; }
             const int n = min(G, pe - pc);
             for (int u0 = 0; u0 < n; u0 += kNumDepth) {
                 // issue the B loads of kNumDepth steps, then accumulate them in order
-                int jv[kNumDepth], q1v[kNumDepth];
+                int jv[kNumDepth];
                 double bv[kNumDepth], av[kNumDepth];
+                uint32_t longm = 0;   // steps whose row of B is longer than G
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) {
-                    jv[d] = -1; bv[d] = 0.0; av[d] = 0.0; q1v[d] = 0;
+                    jv[d] = -1; bv[d] = 0.0; av[d] = 0.0;
                     if (u0 + d < n) {
                         const int4 pr = par[u0 + d];
+                        const int q0 = pr.x, q1 = pr.y;
                         av[d] = __hiloint2double(pr.w, pr.z);
-                        q1v[d] = pr.y;
-                        const int q = pr.x + lane;
-                        if (q < pr.y) { jv[d] = bci[q]; bv[d] = bval[q]; }
+                        if (q1 - q0 > G) longm |= 1u << d;
+                        const int q = q0 + lane;
+                        if (q < q1) { jv[d] = bci[q]; bv[d] = bval[q]; }
                     }
                 }
                 // positions first (independent LDS reads), then the adds in step
@@ -166,15 +263,16 @@ __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
                 // in ascending k. The LDS fp64 add rounds like a plain add.
                 int posv[kNumDepth];
 #pragma unroll
-                for (int d = 0; d < kNumDepth; ++d) posv[d] = jv[d] >= 0 ? pos_lookup(tab, logcap, jv[d]) : -2;
+                for (int d = 0; d < kNumDepth; ++d) posv[d] = jv[d] >= 0 ? tab.lookup(logcap, jv[d]) : -2;
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) {
                     if (posv[d] >= 0) atomicAdd(acc + posv[d], av[d] * bv[d]);
                     else if (posv[d] == -1) bad = true;
-                    if (u0 + d < n && q1v[d] - par[u0 + d].x > G) {   // rows of B longer than G
-                        const int q0 = par[u0 + d].x;
-                        for (int q = q0 + G + lane; q < q1v[d]; q += G) {
-                            const int pos = pos_lookup(tab, logcap, bci[q]);
+                    if ((longm >> d) & 1u) {
+                        const int4 pr = par[u0 + d];
+                        const int q0 = pr.x, q1 = pr.y;
+                        for (int q = q0 + G + lane; q < q1; q += G) {
+                            const int pos = tab.lookup(logcap, bci[q]);
                             if (pos >= 0) atomicAdd(acc + pos, av[d] * bval[q]);
                             else bad = true;
                         }
@@ -187,6 +285,7 @@ __global__ __launch_bounds__(kWG) void k_num_lds(Batch b, Sched sc, int bin)
         if (active)
             for (int e = lane; e < nc; e += G) cval[cs + e] = acc[e];
         nwave_sync();
+        task = task_n;
     }
 }
 
@@ -258,16 +357,33 @@ static int persistent_grid_n(K kernel, int threads)
     return cus * per_cu;
 }
 
+template <int G, int CAP, bool PACK, bool MULTI>
+static void launch_num_variant(const Batch &b, const Sched &sc, int bin, hipStream_t s)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK), W);
+    static int grid = persistent_grid_n(k_num_lds<G, CAP, PACK, MULTI>, NW * kWave);
+    static char name[64];
+    if (!name[0]) snprintf(name, sizeof(name), "num_lds_G%d_C%d%s%s", G, CAP, PACK ? "_p" : "", MULTI ? "_b" : "");
+    ProfScope ps(name, s);
+    hipLaunchKernelGGL((k_num_lds<G, CAP, PACK, MULTI>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
+}
+
+template <int G, int CAP, bool PACK>
+static void launch_num_multi(const Batch &b, const Sched &sc, int bin, hipStream_t s)
+{
+    if (b.nprob > 1) launch_num_variant<G, CAP, PACK, true>(b, sc, bin, s);
+    else launch_num_variant<G, CAP, PACK, false>(b, sc, bin, s);
+}
+
+// The packed table needs every column index below PackBits<CAP>::kMaxCols.
 template <int G, int CAP>
 static void launch_num_class(const Batch &b, const Sched &sc, int bin, hipStream_t s)
 {
-    constexpr int W = kWave / G;
-    constexpr int NW = nw_num(CAP * 12 + G * 16, W);
-    static int grid = persistent_grid_n(k_num_lds<G, CAP>, NW * kWave);
-    static char name[64];
-    if (!name[0]) snprintf(name, sizeof(name), "num_lds_G%d_C%d", G, CAP);
-    ProfScope ps(name, s);
-    hipLaunchKernelGGL((k_num_lds<G, CAP>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
+    if (b.max_ncols > 0 && (uint32_t)b.max_ncols <= PackBits<CAP>::kMaxCols)
+        launch_num_multi<G, CAP, true>(b, sc, bin, s);
+    else
+        launch_num_multi<G, CAP, false>(b, sc, bin, s);
 }
 
 void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s)

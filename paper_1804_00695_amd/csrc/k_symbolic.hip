@@ -59,10 +59,14 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
     constexpr int ROWB = FILL ? CAP * 12 : CAP * 8;
     constexpr int NW = nw_for(ROWB, W);
     constexpr int LIST = FILL ? CAP / 2 : 1;
-    __shared__ __attribute__((aligned(16))) uint32_t s_key[NW * W * CAP];
+    // the fill pass's (set, mask) lists and counters follow the keys; the
+    // count pass allocates nothing beyond the two tables, so that four
+    // 32 KB workgroups of the largest-volume class fit one CU with room for a fifth
+    constexpr int EXTRA = FILL ? NW * W * (2 * LIST + 1) : 0;
+    __shared__ __attribute__((aligned(16))) uint32_t s_key[NW * W * CAP + EXTRA];
     __shared__ __attribute__((aligned(16))) uint32_t s_msk[NW * W * CAP];
-    __shared__ uint2 s_list[NW * W * LIST];
-    __shared__ int s_cnt[NW * W];
+    uint2 *s_list = (uint2 *)(s_key + NW * W * CAP);
+    int *s_cnt = (int *)(s_key + NW * W * CAP + NW * W * 2 * LIST);
 
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;   // launched with NW waves; guard anyway
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
         } else {
             for (int h = lane; h < cap; h += G) { key[h] = kEmptyKey; msk[h] = 0u; }
         }
-        if (lane == 0) s_cnt[rs] = 0;
+        if (FILL && lane == 0) s_cnt[rs] = 0;
         wave_sync();
         if (active) {
             const MLS_G int32_t *__restrict__ aci = gp(P.aci);

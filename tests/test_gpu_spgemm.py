@@ -23,6 +23,7 @@ def _reset_options():
     mls.set_option(mls._abi.OPT_FORCE_SPILL, 0)
     mls.set_option(mls._abi.OPT_GROUP_SIZE, 0)
     mls.set_option(mls._abi.OPT_VALIDATE, 1)
+    mls.set_option(mls._abi.OPT_WIDE_TABLE, 0)
 
 
 def gpu_product(A, B):
@@ -105,6 +106,40 @@ def test_forced_spill_identical():
     mls.set_option(mls._abi.OPT_FORCE_SPILL, 1)
     check(A, A)
     check(synth.poisson_csr(300, 300, 5.0, 9), synth.poisson_csr(300, 400, 5.0, 10))
+
+
+def test_wide_table_identical():
+    # the 8-byte (column, position) slots, which products with many columns use
+    mls.set_option(mls._abi.OPT_WIDE_TABLE, 1)
+    A = synth.stencil27_3d(9, amp=0.1)
+    check(A, A)
+    check(wide_rows(64, 6000, 120, 5), synth.poisson_csr(6000, 20000, 8.0, 99))
+    check(synth.poisson_csr(500, 400, 6.0, 7), synth.poisson_csr(400, 450, 12.0, 8))
+
+
+def with_last_column(B):
+    """B with column ncols-1 present in every row (the largest key a table holds)."""
+    rows, vals = [], []
+    for k in range(B.nrows):
+        c = B.col_idx[B.row_ptr[k]:B.row_ptr[k + 1]]
+        v = B.values[B.row_ptr[k]:B.row_ptr[k + 1]]
+        if len(c) == 0 or c[-1] != B.ncols - 1:
+            c = np.append(c, B.ncols - 1)
+            v = np.append(v, 0.5 + k % 7)
+        rows.append(c)
+        vals.append(v)
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    return synth.Csr(B.nrows, B.ncols, rp, np.concatenate(rows).astype(np.int32), np.concatenate(vals))
+
+
+@pytest.mark.parametrize("ncols", [(1 << 21) - 1, 1 << 21, (1 << 23) - 1, 1 << 23, (1 << 25) - 1, 1 << 25])
+def test_packed_table_column_limits(ncols):
+    # row sizes in all three LDS classes; the packed slots hold column indices
+    # below 2^21 - 1, 2^23 - 1 and 2^25 - 1 for the classes of 4096, 1024 and
+    # 256 slots, and the wide slots take over from there
+    B = with_last_column(synth.poisson_csr(3000, ncols, 6.0, 31))
+    for per_row, seed in ((10, 1), (60, 2), (200, 3)):
+        check(wide_rows(24, 3000, per_row, seed), B)
 
 
 def test_row_work_and_compress():
@@ -208,8 +243,9 @@ def raw_symbolic(A, B, ws_bytes_fn=lambda full, minimal: full, separate_fill_ws=
 @pytest.mark.parametrize("mode", ["scratch", "separate_ws", "no_scratch_room", "fill_twice"])
 def test_symbolic_fill_paths(mode):
     A = synth.stencil27_3d(9, amp=0.1)
-    B = wide_rows(300, 729, 60, 5)          # rows of C with > 64 words overflow the scratch
-    for X, Y in ((A, A), (synth.poisson_csr(400, 729, 20.0, 3), B)):
+    B = wide_rows(729, 20000, 60, 5)        # rows of C with > 64 words overflow the scratch
+    # rows with 0 or 1 entries of A fit the scratch, longer ones overflow it
+    for X, Y in ((A, A), (synth.poisson_csr(400, 729, 1.5, 3), B)):
         R, _ = oracle.spgemm(X, Y, with_abs=False)
         kw = {}
         if mode == "separate_ws":
