@@ -53,6 +53,8 @@ Layout make_layout(int64_t nprob, int64_t na, int64_t nb, int64_t zb, int64_t ma
     L.val = take(sizeof(int32_t) * (size_t)std::max<int64_t>(na, 1));
     L.cls = take((size_t)std::max<int64_t>(na, 1));
     L.perm = take(sizeof(int32_t) * (size_t)std::max<int64_t>(na, 1));
+    L.nblk = (int32_t)((std::max<int64_t>(na, 1) + kBinRowsPerWG - 1) / kBinRowsPerWG);
+    L.blk = take(sizeof(int32_t) * (size_t)kNumBins * (size_t)L.nblk);
     L.prefix = take(sizeof(int64_t) * (size_t)(na + 1));
     L.tiles = take(sizeof(int64_t) * (size_t)scan_tiles((int)std::min<int64_t>(na, 0x7fffffff)));
     if (need_bw) {
@@ -97,7 +99,8 @@ Sched make_sched(char *ws, const Layout &L)
     Sched sc;
     sc.err = (uint32_t *)(ws + L.hdr + kHdrErr);
     sc.bin_count = (int32_t *)(ws + L.hdr + kHdrBinCount);
-    sc.bin_cursor = (int32_t *)(ws + L.hdr + kHdrBinCursor);
+    sc.blk_cnt = (int32_t *)(ws + L.blk);
+    sc.nblk = L.nblk;
     sc.task_cursor = (int32_t *)(ws + L.hdr + kHdrTaskCursor);
     sc.val = (int32_t *)(ws + L.val);
     sc.cls = (uint8_t *)(ws + L.cls);

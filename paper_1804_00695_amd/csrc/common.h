@@ -76,7 +76,9 @@ struct Batch {
 struct Sched {
     uint32_t *err;
     int32_t *bin_count;     // [kNumBins]
-    int32_t *bin_cursor;    // [kNumBins]
+    int32_t *blk_cnt;       // [kNumBins * nblk]: rows of each bin per block of kBinRowsPerWG rows,
+                            // then (after the bin scan) where those rows start in perm
+    int32_t nblk;
     int32_t *task_cursor;   // [kNumBins * kXcd]
     int32_t *val;           // per global row: size used for binning / result
     uint8_t *cls;           // per global row: bin
@@ -89,6 +91,11 @@ struct Sched {
 };
 
 constexpr int kScratchWords = 64;
+
+// Rows per binning block: every binning kernel assigns rows [b * kBinRowsPerWG,
+// (b + 1) * kBinRowsPerWG) to workgroup b and leaves the block's row count per
+// bin in blk_cnt, so that the bin scan and the scatter need no global atomics.
+constexpr int kBinRowsPerWG = 1024;
 
 // Pointers read out of descriptors are generic; loads through them compile
 // to flat instructions, which make the compiler wait on LDS and vector memory
@@ -153,6 +160,17 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// Row at position pos of perm, or -1 (and an error bit) when the position or
+// the row lies outside the batch -- which consistent bins never produce; the
+// kernels then skip the row instead of dereferencing a bad index.
+__device__ __forceinline__ int bin_row(const int32_t *perm, uint32_t *err, int na, int pos)
+{
+    if ((unsigned)pos >= (unsigned)na) { atomicOr(err, kErrTable); return -1; }
+    const int g = gp(perm)[pos];
+    if ((unsigned)g >= (unsigned)na) { atomicOr(err, kErrTable); return -1; }
+    return g;
+}
+
 // Bin start = exclusive prefix of the bin counts.
 __device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
 {
@@ -195,6 +213,7 @@ __device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg)
 __device__ __forceinline__ int next_task_wave(int32_t *cursor, int ntasks, TaskIter &it)
 {
     (void)ntasks;
+    if (it.lo >= it.hi) return -1;   // empty slab: no counter traffic
     for (;;) {
         if (it.left > 0) {
             const int t = it.cur;

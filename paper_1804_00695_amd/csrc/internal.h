@@ -25,13 +25,13 @@ extern thread_local int g_last_hip_error;
 constexpr size_t kHdrBytes = 1024;
 constexpr size_t kHdrErr = 0;
 constexpr size_t kHdrBinCount = 64;
-constexpr size_t kHdrBinCursor = 128;
 constexpr size_t kHdrTaskCursor = 192;   // kNumBins * kXcd int32
 constexpr size_t kHdrTotal = 512;        // uint64
 
 struct Layout {
     size_t hdr = 0, totals = 0, nnz_tab = 0, probs = 0, abase = 0, bbase = 0;
-    size_t val = 0, cls = 0, perm = 0, prefix = 0, tiles = 0;
+    size_t val = 0, cls = 0, perm = 0, prefix = 0, tiles = 0, blk = 0;
+    int32_t nblk = 0;
     size_t bw = 0, bwc = 0, spill = 0;
     int64_t spill_words = 0;
     int spill_slots = 0;

@@ -76,7 +76,6 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
     const MLS_G int32_t *__restrict__ wci = gp(P.cci);
     const MLS_G double *__restrict__ wval = gp(P.cval);
     MLS_G double *__restrict__ gdA = gpw(dA);
-    const MLS_G int32_t *perm = gp(sc.perm);
     const MLS_G int32_t *val = gp(sc.val);
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
@@ -86,8 +85,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
         int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
         if (task < 0) break;
         const int r = task * W + slot;
-        const bool active = r < n_bin;
-        const int i = active ? perm[start + r] : 0;
+        const int gi = r < n_bin ? bin_row(sc.perm, sc.err, b.na, start + r) : -1;
+        const bool active = gi >= 0;
+        const int i = active ? gi : 0;
         const int nw = active ? val[i] : 0;
         int logcap = ilog2_ceil(2 * nw);
         if (logcap < 5) logcap = 5;
@@ -173,7 +173,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_spill(Batch b, Sched sc, double *dA
     const int n_bin = gp(sc.bin_count)[kBinSpill];
     const int start = bin_start(sc.bin_count, kBinSpill);
     for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
-        const int i = gp(sc.perm)[start + r];
+        const int i = bin_row(sc.perm, sc.err, b.na, start + r);
+        if (i < 0) continue;
         const int w0 = gp(P.crp)[i], nw = gp(P.crp)[i + 1] - w0;
         const MLS_G int32_t *wc = gp(P.cci) + w0;
         const MLS_G double *wvv = gp(P.cval) + w0;

@@ -179,7 +179,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
     double *acc = s_acc + rs * (CAP / 2);
     int4 *par = s_par + rs * G;
 
-    const MLS_G int32_t *perm = gp(sc.perm);
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
@@ -188,13 +187,14 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
     // row starts and its metadata (size, row pointers) in the middle of the
     // row, so a row starts with its dependent index loads already done.
     int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-    int g_cur = 0;
-    if (task >= 0 && task * W + slot < n_bin) g_cur = perm[start + task * W + slot];
-    RowMeta m = row_meta<MULTI>(b, sc, task >= 0 && task * W + slot < n_bin, g_cur);
+    int g_cur = -1;
+    if (task >= 0 && task * W + slot < n_bin) g_cur = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
+    RowMeta m = row_meta<MULTI>(b, sc, g_cur >= 0, g_cur);
     while (task >= 0) {
         const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        const bool act_n = task_n >= 0 && task_n * W + slot < n_bin;
-        const int g_n = act_n ? perm[start + task_n * W + slot] : 0;
+        const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
+                            ? bin_row(sc.perm, sc.err, b.na, start + task_n * W + slot) : -1;
+        const bool act_n = g_n >= 0;
 
         const bool active = m.active;
         const Prob P = prob_of<MULTI>(b, m.t);
@@ -304,7 +304,8 @@ __global__ __launch_bounds__(kWG) void k_num_spill(Batch b, Sched sc)
     const int n_bin = gp(sc.bin_count)[kBinSpill];
     const int start = bin_start(sc.bin_count, kBinSpill);
     for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
-        int g = gp(sc.perm)[start + r];
+        const int g = bin_row(sc.perm, sc.err, b.na, start + r);
+        if (g < 0) continue;
         int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
         const Prob P = get_prob(b, t);
         int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);

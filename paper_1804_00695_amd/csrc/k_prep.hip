@@ -211,7 +211,14 @@ __device__ __forceinline__ int class_of(int mode, int64_t size, int force_spill)
     return kBinSpill;
 }
 
-constexpr int kBinRowsPerWG = 256;   // rows per workgroup: one set of global atomics each
+constexpr int kBinRG = 8;                    // lanes per row where the size is gathered
+constexpr int kBinSlots = kWG / kBinRG;      // rows in flight per workgroup
+
+// Per-block bin counts (LDS) written to blk_cnt[c * nblk + block].
+__device__ __forceinline__ void bin_write_counts(const Sched &sc, const int *cnt)
+{
+    if (threadIdx.x < kNumBins) gpw(sc.blk_cnt)[threadIdx.x * sc.nblk + (int)blockIdx.x] = cnt[threadIdx.x];
+}
 
 __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int force_spill,
                                              unsigned long long *total)
@@ -221,9 +228,11 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
     if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) tsum = 0;
     __syncthreads();
+    const int g0 = blockIdx.x * kBinRowsPerWG;
     if (mode == kModeNumeric) {   // size = nnz(C_i): one thread per row
-        const int g = blockIdx.x * kBinRowsPerWG + threadIdx.x;
-        if (g < b.na) {
+        for (int r = threadIdx.x; r < kBinRowsPerWG; r += kWG) {
+            const int g = g0 + r;
+            if (g >= b.na) break;
             const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
             const Prob P = get_prob(b, t);
             const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
@@ -234,47 +243,51 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
             atomicAdd(&cnt[c], 1);
         }
         __syncthreads();
-        if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(sc.bin_count + threadIdx.x, cnt[threadIdx.x]);
+        bin_write_counts(sc, cnt);
         return;
     }
-    const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
-    for (int r = slot; r < kBinRowsPerWG; r += kRowsPerWG) {
-        const int g = blockIdx.x * kBinRowsPerWG + r;
+    const int slot = threadIdx.x / kBinRG, lane = threadIdx.x % kBinRG;
+    for (int r = slot; r < kBinRowsPerWG; r += kBinSlots) {
+        const int g = g0 + r;
         if (g >= b.na) break;   // uniform per row group
         const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
         const Prob P = get_prob(b, t);
         const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        // fill pass: rows whose words the count pass kept are expanded, not binned
+        const bool from_scratch = mode == kModeFill && sc.scr && gp(sc.scnt)[g] >= 0;
         int64_t size = 0;
-        if (mode != kModeNumeric) {
+        if (!from_scratch) {
             const MLS_G int32_t *__restrict__ aci = gp(P.aci);
             const MLS_G int32_t *__restrict__ brp = gp(P.brp);
             const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
             const int k_lo = P.k_lo, k_hi = P.k_hi;
             const int s = gp(P.arp)[i] - P.a_off, e = gp(P.arp)[i + 1] - P.a_off;
-            for (int p = s + lane; p < e; p += kRowG) {
+            for (int p = s + lane; p < e; p += kBinRG) {
                 const int k = aci[p];
                 if (k < k_lo || k >= k_hi) continue;
                 const int kl = k - k_lo;
                 size += mode == kModeWork ? (int64_t)(brp[kl + 1] - brp[kl]) : (int64_t)bwc[kl];
             }
-            size = group_sum<kRowG>(size);
+            size = group_sum<kBinRG>(size);
         }
         if (lane == 0) {
-            int64_t nc = 0;
-            if (mode == kModeFill || mode == kModeNumeric) nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
-            if (mode == kModeFill) size = size < nc ? size : nc;
-            if (mode == kModeNumeric) size = nc;
             int c;
-            if (mode == kModeWork) {
+            if (from_scratch) {
                 c = kBinEmpty;
-                if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
-                atomicAdd(&tsum, (unsigned long long)size);
-            } else if (mode == kModeFill && sc.scr && gp(sc.scnt)[g] >= 0) {
-                c = kBinEmpty;   // expanded from the count pass's scratch words
             } else {
-                c = class_of(mode, size, force_spill);
-                // rows without work get no symbolic kernel: their scratch is empty
-                if (mode == kModeCount && sc.scr && c == kBinEmpty) gpw(sc.scnt)[g] = 0;
+                if (mode == kModeFill) {
+                    const int64_t nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
+                    size = size < nc ? size : nc;
+                }
+                if (mode == kModeWork) {
+                    c = kBinEmpty;
+                    if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
+                    atomicAdd(&tsum, (unsigned long long)size);
+                } else {
+                    c = class_of(mode, size, force_spill);
+                    // rows without work get no symbolic kernel: their scratch is empty
+                    if (mode == kModeCount && sc.scr && c == kBinEmpty) gpw(sc.scnt)[g] = 0;
+                }
             }
             if (size >= 0x7fffffffLL) size = 0x7fffffff;
             gpw(sc.val)[g] = (int32_t)size;
@@ -283,32 +296,100 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
         }
     }
     __syncthreads();
-    if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(sc.bin_count + threadIdx.x, cnt[threadIdx.x]);
+    bin_write_counts(sc, cnt);
     if (threadIdx.x == 0 && total && tsum) atomicAdd(total, tsum);
 }
 
-// Group the rows by bin: perm[bin_start[c] + ...] = global row. Rows of one
-// workgroup (256 consecutive rows) stay together, so neighbouring rows are
-// processed close in time.
-__global__ void k_scatter(int na, Sched sc)
+// One workgroup: bin totals into bin_count, and every block's count per bin
+// replaced by the position in perm where that block's rows of the bin start
+// (bins in order, blocks in order inside a bin). Only the nb blocks of this
+// launch count: a launch over fewer rows than the workspace was laid out for
+// (a chunk part) leaves the counts of later blocks from earlier launches.
+__global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
 {
-    __shared__ int cnt[kNumBins];
-    __shared__ int base[kNumBins];
-    if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    int c = -1, pos = 0;
-    if (g < na) {
-        c = gp(sc.cls)[g];
-        pos = atomicAdd(&cnt[c], 1);
+    __shared__ int64_t s_red[kWG / kWave];
+    __shared__ int64_t s_tot[kNumBins];
+    __shared__ int64_t s_carry;
+    MLS_G int32_t *blk = gpw(sc.blk_cnt);
+    const int stride = sc.nblk;
+    const int nblk = nb < stride ? nb : stride;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = 0; c < kNumBins; ++c) {
+        int64_t v = 0;
+        for (int x = threadIdx.x; x < nblk; x += kWG) v += blk[c * stride + x];
+        v = group_sum<kWave>(v);
+        if (lane == 0) s_red[wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int w = 0; w < kWG / kWave; ++w) t += s_red[w];
+            s_tot[c] = t;
+        }
+        __syncthreads();
     }
+    if (threadIdx.x < kNumBins) gpw(sc.bin_count)[threadIdx.x] = (int32_t)s_tot[threadIdx.x];
+    if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    if (threadIdx.x < kNumBins) {
-        int n = cnt[threadIdx.x];
-        base[threadIdx.x] = n ? atomicAdd(sc.bin_cursor + threadIdx.x, n) + bin_start(sc.bin_count, threadIdx.x) : 0;
+    for (int c = 0; c < kNumBins; ++c) {
+        for (int x0 = 0; x0 < nblk; x0 += kWG) {
+            const int x = x0 + threadIdx.x;
+            const int64_t v = x < nblk ? blk[c * stride + x] : 0;
+            int64_t incl = v;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int64_t y = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += y;
+            }
+            if (lane == 63) s_red[wave] = incl;
+            __syncthreads();
+            int64_t off = s_carry;
+            for (int w = 0; w < wave; ++w) off += s_red[w];
+            if (x < nblk) blk[c * stride + x] = (int32_t)(off + incl - v);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int64_t t = 0;
+                for (int w = 0; w < kWG / kWave; ++w) t += s_red[w];
+                s_carry += t;
+            }
+            __syncthreads();
+        }
     }
+}
+
+// Group the rows by bin: perm[start of bin c ...] = global rows of bin c in
+// ascending order (ranks by wave ballots, so the order is deterministic).
+__global__ __launch_bounds__(kWG) void k_scatter(int na, Sched sc)
+{
+    __shared__ int s_wcnt[kWG / kWave][kNumBins];
+    __shared__ int s_base[kNumBins];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < kNumBins) s_base[threadIdx.x] = gp(sc.blk_cnt)[threadIdx.x * sc.nblk + (int)blockIdx.x];
     __syncthreads();
-    if (c >= 0) gpw(sc.perm)[base[c] + pos] = g;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int r0 = 0; r0 < kBinRowsPerWG; r0 += kWG) {
+        const int g = blockIdx.x * kBinRowsPerWG + r0 + (int)threadIdx.x;
+        const int c = g < na ? (int)gp(sc.cls)[g] : -1;
+        int rank = 0;
+#pragma unroll
+        for (int cc = 0; cc < kNumBins; ++cc) {
+            const unsigned long long m = __ballot(c == cc);
+            if (c == cc) rank = __popcll(m & below);
+            if (lane == 0) s_wcnt[wave][cc] = __popcll(m);
+        }
+        __syncthreads();
+        if (c >= 0) {
+            int off = s_base[c];
+            for (int w = 0; w < wave; ++w) off += s_wcnt[w][c];
+            gpw(sc.perm)[off + rank] = g;
+        }
+        __syncthreads();
+        if (threadIdx.x < kNumBins) {
+            int t = 0;
+            for (int w = 0; w < kWG / kWave; ++w) t += s_wcnt[w][threadIdx.x];
+            s_base[threadIdx.x] += t;
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -450,15 +531,17 @@ void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsi
         ProfScope ps("bin", s);
         hipLaunchKernelGGL(k_bin, dim3(nblk(b.na, kBinRowsPerWG)), dim3(kWG), 0, s, b, mode, sc, force_spill, total);
     }
-    ProfScope ps("scatter", s);
-    hipLaunchKernelGGL(k_scatter, dim3(nblk(b.na, kWG)), dim3(kWG), 0, s, b.na, sc);
+    launch_scatter(b.na, sc, s);
 }
 
+// Bin scan and scatter after a binning kernel (blocks of kBinRowsPerWG rows).
 void launch_scatter(int na, const Sched &sc, hipStream_t s)
 {
     if (na <= 0) return;
     ProfScope ps("scatter", s);
-    hipLaunchKernelGGL(k_scatter, dim3(nblk(na, kWG)), dim3(kWG), 0, s, na, sc);
+    const int nb = nblk(na, kBinRowsPerWG);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kWG), 0, s, sc, nb);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kWG), 0, s, na, sc);
 }
 
 int scan_tiles(int n) { return nblk(n > 0 ? n : 1, kScanTile); }

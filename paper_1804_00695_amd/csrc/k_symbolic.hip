@@ -52,6 +52,28 @@ __device__ __forceinline__ void set_insert(uint32_t *key, uint32_t *msk, int log
     atomicOr(err, kErrTable);
 }
 
+// Where a row of the bin lives: product t, local row i, its table size
+// bound and its A entry range [ps, pe) (local); g < 0 for no row.
+struct SymRow {
+    int g, t, i, size, ps, pe;
+};
+
+__device__ __forceinline__ SymRow sym_row(const Batch &b, const Sched &sc, int g)
+{
+    SymRow m{g, 0, 0, 0, 0, 0};
+    if (g < 0) return m;
+    m.i = g;
+    if (b.nprob > 1) {
+        m.t = find_prob(b.abase, b.nprob, g);
+        m.i = g - gp(b.abase)[m.t];
+    }
+    const Prob P = get_prob(b, m.t);
+    m.size = gp(sc.val)[g];
+    m.ps = gp(P.arp)[m.i] - P.a_off;
+    m.pe = gp(P.arp)[m.i + 1] - P.a_off;
+    return m;
+}
+
 template <int G, int CAP, bool FILL>
 __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
 {
@@ -77,22 +99,27 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
     uint32_t *msk = s_msk + rs * CAP;
     uint2 *list = s_list + rs * LIST;
 
-    const MLS_G int32_t *perm = gp(sc.perm);
     MLS_G int32_t *val = gpw(sc.val);
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
     TaskIter it = task_iter(ntasks, NW);
-    for (;;) {
-        int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        if (task < 0) break;
-        const int r = task * W + slot;
-        const bool active = r < n_bin;
-        int g = active ? perm[start + r] : 0;
-        int t = (!active || b.nprob == 1) ? 0 : find_prob(b.abase, b.nprob, g);
+    // rows are software-pipelined: the next row's perm entry is loaded when a
+    // row starts, its size and row pointers once the row's words are inserted
+    int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+    int g_first = -1;
+    if (task >= 0 && task * W + slot < n_bin) g_first = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
+    SymRow m = sym_row(b, sc, g_first);
+    while (task >= 0) {
+        const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+        const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
+                            ? bin_row(sc.perm, sc.err, b.na, start + task_n * W + slot) : -1;
+        const bool active = m.g >= 0;
+        const int g = active ? m.g : 0;
+        const int t = m.t;
         const Prob P = get_prob(b, t);
-        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
-        int size = active ? val[g] : 0;
+        const int i = m.i;
+        const int size = m.size;
         int logcap = ilog2_ceil(FILL ? 2 * size : size);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
@@ -114,7 +141,7 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
             const MLS_G u32x2 *__restrict__ bw = (const MLS_G u32x2 *)P.bw;
             const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
             const int b_off = P.b_off, k_lo = P.k_lo, k_hi = P.k_hi;
-            int ps = gp(P.arp)[i] - P.a_off, pe = gp(P.arp)[i + 1] - P.a_off;
+            const int ps = m.ps, pe = m.pe;
             for (int p = ps + lane; p < pe; p += G) {
                 int k = aci[p];
                 if (k < k_lo || k >= k_hi) continue;
@@ -132,6 +159,7 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
                 }
             }
         }
+        m = sym_row(b, sc, g_n);
         wave_sync();
         if (!FILL) {
             // popcount of the union and number of occupied slots; each lane owns
@@ -229,6 +257,7 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
             }
         }
         wave_sync();
+        task = task_n;
     }
 }
 
@@ -242,7 +271,8 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
     const int n_bin = gp(sc.bin_count)[kBinSpill];
     const int start = bin_start(sc.bin_count, kBinSpill);
     for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
-        int g = gp(sc.perm)[start + r];
+        const int g = bin_row(sc.perm, sc.err, b.na, start + r);
+        if (g < 0) continue;
         int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
         const Prob P = get_prob(b, t);
         int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
@@ -321,64 +351,70 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
     }
 }
 
-// Fill pass from the count pass's scratch: G lanes per row load the row's
-// words, place each word at the popcount sum of the words with smaller sets
-// and expand its bits into ascending columns. Rows without scratch words
-// (scnt < 0) are left to the recomputing fill kernels.
-template <int G>
+// Fill pass from the count pass's scratch: one wave per row, lane e holding
+// word e (a row keeps at most kScratchWords = 64 words). A word's output
+// offset is the popcount sum of the words with smaller sets, accumulated from
+// lane reads (no LDS); its bits then expand into ascending columns. The loads
+// of the next row (its word count, all 64 scratch slots, its C row bounds)
+// are issued before the current row's stores, so that waiting for them never
+// waits for those stores. Rows without scratch words (scnt < 0) are left to
+// the recomputing fill kernels.
+static_assert(kScratchWords == kWave, "one scratch word per lane");
+
+struct ExpandRow {
+    int n, cs, ce;
+    u32x2 w;
+};
+
+__device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc, int g, int lane)
+{
+    ExpandRow r;
+    r.n = -1; r.cs = 0; r.ce = 0;
+    r.w.x = 0u; r.w.y = 0u;
+    if (g >= b.na) return r;
+    r.n = gp(sc.scnt)[g];
+    r.w = ((const MLS_G u32x2 *)sc.scr)[(int64_t)g * kScratchWords + lane];
+    const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+    const Prob P = get_prob(b, t);
+    const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+    r.cs = gp(P.crp)[i] - P.c_off;
+    r.ce = gp(P.crp)[i + 1] - P.c_off;
+    return r;
+}
+
 __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
 {
-    constexpr int W = kWave / G;
-    constexpr int NW = kWG / kWave;
-    __shared__ uint2 s_list[NW * W * kScratchWords];
-    const int wave = threadIdx.x >> 6;
-    const int lw = threadIdx.x & 63;
-    const int slot = lw / G, lane = lw % G;
-    const int rs = wave * W + slot;
-    uint2 *list = s_list + rs * kScratchWords;
-    const int rows_per_wg = NW * W;
-    for (int g0 = blockIdx.x * rows_per_wg; g0 < b.na; g0 += gridDim.x * rows_per_wg) {
-        const int g = g0 + rs;
-        const bool row_ok = g < b.na;
-        const int n = row_ok ? gp(sc.scnt)[g] : -1;
-        if (n > 0) {
-            const MLS_G u32x2 *src = (const MLS_G u32x2 *)sc.scr + (int64_t)g * kScratchWords;
-            for (int e = lane; e < n; e += G) {
-                u32x2 w = src[e];
-                list[e] = make_uint2(w.x, w.y);
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int lane = threadIdx.x & 63;
+    const int nw = (int)gridDim.x * (kWG / kWave);
+    int g = (int)((blockIdx.x * kWG + threadIdx.x) >> 6);
+    ExpandRow cur = expand_load(b, sc, g, lane);
+    for (; g < b.na; g += nw) {
+        const ExpandRow nxt = expand_load(b, sc, g + nw, lane);
+        const int n = __builtin_amdgcn_readfirstlane(cur.n);   // uniform: one row per wave
         if (n > 0) {
             const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
-            const Prob P = get_prob(b, t);
-            const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
-            const int cs = gp(P.crp)[i] - P.c_off;
-            const int ce = gp(P.crp)[i + 1] - P.c_off;
-            MLS_G int32_t *__restrict__ cci = gpw(P.cci);
-            for (int e = lane; e < n; e += G) {
-                const uint2 me = list[e];
-                int off = 0;
-                for (int f = 0; f < n; ++f) {
-                    const uint2 o = list[f];
-                    off += (o.x < me.x) ? __popc(o.y) : 0;
-                }
-                uint32_t m = me.y;
-                int pos = cs + off;
+            MLS_G int32_t *__restrict__ cci = gpw(get_prob(b, t).cci);
+            const uint32_t set = cur.w.x;
+            const int pc = lane < n ? __popc(cur.w.y) : 0;
+            int off = 0;
+            for (int f = 0; f < n; ++f) {
+                const uint32_t sf = (uint32_t)__builtin_amdgcn_readlane((int)set, f);
+                const int pf = __builtin_amdgcn_readlane(pc, f);
+                off += sf < set ? pf : 0;
+            }
+            if (lane < n) {
+                uint32_t m = cur.w.y;
+                int pos = cur.cs + off;
                 while (m) {
                     const int bit = __ffs(m) - 1;
-                    if (pos < ce) cci[pos] = (int32_t)(me.x * 32u + (uint32_t)bit);
+                    if (pos < cur.ce) cci[pos] = (int32_t)(set * 32u + (uint32_t)bit);
                     else atomicOr(sc.err, kErrStructure);
                     ++pos;
                     m &= m - 1u;
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        cur = nxt;
     }
 }
 
@@ -386,8 +422,8 @@ void launch_sym_expand(const Batch &b, const Sched &sc, hipStream_t s)
 {
     if (b.na <= 0 || !sc.scr) return;
     static int cus = device_cu_count();
-    ProfScope ps("sym_expand_G32", s);
-    hipLaunchKernelGGL(k_sym_expand<32>, dim3(cus * 8), dim3(kWG), 0, s, b, sc);
+    ProfScope ps("sym_expand", s);
+    hipLaunchKernelGGL(k_sym_expand, dim3(cus * 8), dim3(kWG), 0, s, b, sc);
 }
 
 // ---------------------------------------------------------------------------

@@ -55,7 +55,6 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
     const MLS_G int32_t *__restrict__ lci = gp(P.aci);
     const MLS_G u32x2 *__restrict__ bw = (const MLS_G u32x2 *)P.bw;
     const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
-    const MLS_G int32_t *perm = gp(sc.perm);
     const MLS_G int32_t *val = gp(sc.val);
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
@@ -65,8 +64,9 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
         int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
         if (task < 0) break;
         const int r = task * W + slot;
-        const bool active = r < n_bin;
-        const int i = active ? perm[start + r] : 0;
+        const int gi = r < n_bin ? bin_row(sc.perm, sc.err, b.na, start + r) : -1;
+        const bool active = gi >= 0;
+        const int i = active ? gi : 0;
         const int size = active ? val[i] : 0;
         int logcap = ilog2_ceil(2 * size);
         if (logcap < 5) logcap = 5;
@@ -127,7 +127,8 @@ __global__ __launch_bounds__(kWG) void k_tc_spill(Batch b, Sched sc, int64_t *co
     const int start = bin_start(sc.bin_count, kBinSpill);
     const int nwords = (P.ncols + 31) >> 5;
     for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
-        const int i = gp(sc.perm)[start + r];
+        const int i = bin_row(sc.perm, sc.err, b.na, start + r);
+        if (i < 0) continue;
         for (int w = threadIdx.x; w < nwords; w += kWG)
             __hip_atomic_store(bm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
@@ -164,14 +165,15 @@ __global__ __launch_bounds__(kWG) void k_tc_spill(Batch b, Sched sc, int64_t *co
 
 // Bins of L's rows by the word count of row i itself (the size of its hash
 // table); rows without entries count zero triangles.
-__global__ void k_tc_bin(Batch b, Sched sc, int force_spill)
+__global__ __launch_bounds__(kWG) void k_tc_bin(Batch b, Sched sc, int force_spill)
 {
     __shared__ int cnt[kNumBins];
     if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
     __syncthreads();
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < b.na) {
-        const Prob P = b.p0;
+    const Prob P = b.p0;
+    for (int r = threadIdx.x; r < kBinRowsPerWG; r += kWG) {
+        const int i = blockIdx.x * kBinRowsPerWG + r;
+        if (i >= b.na) break;
         int len = gp(P.arp)[i + 1] - gp(P.arp)[i];
         int size = gp(P.bwc)[i];
         int c;
@@ -183,7 +185,7 @@ __global__ void k_tc_bin(Batch b, Sched sc, int force_spill)
         atomicAdd(&cnt[c], 1);
     }
     __syncthreads();
-    if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(sc.bin_count + threadIdx.x, cnt[threadIdx.x]);
+    if (threadIdx.x < kNumBins) gpw(sc.blk_cnt)[threadIdx.x * sc.nblk + (int)blockIdx.x] = cnt[threadIdx.x];
 }
 
 __global__ void k_sum_i64(const int64_t *x, int n, unsigned long long *total)
@@ -226,7 +228,7 @@ static void launch_tc_class(const Batch &b, const Sched &sc, int bin, int64_t *c
 void launch_tc_bin(const Batch &b, const Sched &sc, int force_spill, hipStream_t s)
 {
     if (b.na <= 0) return;
-    int grid = (b.na + kWG - 1) / kWG;
+    int grid = (b.na + kBinRowsPerWG - 1) / kBinRowsPerWG;
     {
         ProfScope ps("tc_bin", s);
         hipLaunchKernelGGL(k_tc_bin, dim3(grid), dim3(kWG), 0, s, b, sc, force_spill);
