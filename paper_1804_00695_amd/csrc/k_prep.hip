@@ -41,53 +41,80 @@ __device__ __forceinline__ uint32_t group_ballot(bool pred, int slot_in_wave)
 // CSR checks over the A rows (which = 0) or B rows (which = 1) of a batch:
 // row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, columns in range and
 // strictly increasing. Column indices outside [0, nnz) are never read.
-__device__ __forceinline__ bool validate_row(const Batch &b, int which, const int64_t *nnz_tab, int g)
-{
-    const int lane = threadIdx.x % kRowG;
-    const int32_t *base = which == 0 ? b.abase : b.bbase;
-    const int t = b.nprob == 1 ? 0 : find_prob(base, b.nprob, g);
-    const Prob P = get_prob(b, t);
-    const int i = g - (b.nprob == 1 ? 0 : gp(base)[t]);
-    const MLS_G int32_t *rp = gp(which == 0 ? P.arp : P.brp);
-    const MLS_G int32_t *ci = gp(which == 0 ? P.aci : P.bci);
-    const int off = which == 0 ? P.a_off : P.b_off;
-    const int ncols = which == 0 ? P.k_hi : P.ncols;
-    const int nrows = which == 0 ? P.nrows : P.krows;
-    const int64_t nnz = gp(nnz_tab)[2 * t + which];
-    const int s = rp[i], e = rp[i + 1];
-    bool bad = false;
-    if (i == 0 && s != off) bad = true;
-    if (i == nrows - 1 && (int64_t)e - off != nnz) bad = true;
-    if (e < s || s < off || (int64_t)e - off > nnz) bad = true;
-    if (!bad) {
-        int carry = -1;
-        for (int q0 = s - off; q0 < e - off; q0 += kRowG) {
-            const int q = q0 + lane;
-            const bool valid = q < e - off;
-            const int c = valid ? ci[q] : 0;
-            int prev = __shfl_up(c, 1, kRowG);
-            if (lane == 0) prev = carry;
-            if (valid && (c < 0 || c >= ncols || c <= prev)) bad = true;
-            carry = __shfl(c, kRowG - 1, kRowG);
-        }
-    }
-    return bad;
-}
-
-constexpr int kLoopRowsPerWG = 256;   // rows per workgroup of the helper kernels
+// One thread per row walks rows of up to kShortRow entries; the wave checks
+// longer rows together, one at a time, 64 entries per step.
+constexpr int kShortRow = 64;
 
 __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
 {
-    const int slot = threadIdx.x / kRowG;
+    const int lane = threadIdx.x & 63;
     const int total = which == 0 ? b.na : b.nb;
-    bool bad_any = false;
-    for (int r = slot; r < kLoopRowsPerWG; r += kRowsPerWG) {
-        const int g = blockIdx.x * kLoopRowsPerWG + r;
-        if (g >= total) break;   // uniform per row group
-        bad_any |= validate_row(b, which, nnz_tab, g);
+    const int g = blockIdx.x * kWG + threadIdx.x;
+    bool bad = false, longrow = false;
+    const int32_t *ci_row = nullptr;   // entries of this thread's row (long rows)
+    int len = 0, ncols = 0;
+    if (g < total) {
+        const int32_t *base = which == 0 ? b.abase : b.bbase;
+        const int t = b.nprob == 1 ? 0 : find_prob(base, b.nprob, g);
+        const Prob P = get_prob(b, t);
+        const int i = g - (b.nprob == 1 ? 0 : gp(base)[t]);
+        const MLS_G int32_t *rp = gp(which == 0 ? P.arp : P.brp);
+        const int32_t *ci = which == 0 ? P.aci : P.bci;
+        const int off = which == 0 ? P.a_off : P.b_off;
+        ncols = which == 0 ? P.k_hi : P.ncols;
+        const int nrows = which == 0 ? P.nrows : P.krows;
+        const int64_t nnz = gp(nnz_tab)[2 * t + which];
+        const int s = rp[i], e = rp[i + 1];
+        if (i == 0 && s != off) bad = true;
+        if (i == nrows - 1 && (int64_t)e - off != nnz) bad = true;
+        if (e < s || s < off || (int64_t)e - off > nnz) bad = true;
+        if (!bad) {
+            len = e - s;
+            ci_row = ci + (s - off);
+            if (len <= kShortRow) {
+                const MLS_G int32_t *c = gp(ci_row);
+                int prev = -1, q = 0;
+                for (; q + 4 <= len; q += 4) {
+                    const int c0 = c[q], c1 = c[q + 1], c2 = c[q + 2], c3 = c[q + 3];
+                    bad |= c0 <= prev || c1 <= c0 || c2 <= c1 || c3 <= c2 || c0 < 0 || c3 >= ncols;
+                    prev = c3;
+                }
+                for (; q < len; ++q) {
+                    const int cq = c[q];
+                    bad |= cq <= prev || cq < 0 || cq >= ncols;
+                    prev = cq;
+                }
+            } else {
+                longrow = true;
+            }
+        }
     }
-    if (bad_any) atomicOr(err, kErrBadCsr);
+    unsigned long long lm = __ballot(longrow);
+    while (lm) {
+        const int src = __ffsll((long long)lm) - 1;
+        lm &= lm - 1ull;
+        const int n = __builtin_amdgcn_readlane(len, src);
+        const int nc = __builtin_amdgcn_readlane(ncols, src);
+        const uint64_t pa = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)ci_row >> 32), src) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint64_t)ci_row, src);
+        const MLS_G int32_t *c = (const MLS_G int32_t *)pa;
+        int carry = -1;
+        bool bl = false;
+        for (int q0 = 0; q0 < n; q0 += kWave) {
+            const int q = q0 + lane;
+            const bool valid = q < n;
+            const int cq = valid ? c[q] : 0;
+            int prev = __shfl_up(cq, 1, kWave);
+            if (lane == 0) prev = carry;
+            if (valid && (cq < 0 || cq >= nc || cq <= prev)) bl = true;
+            carry = __shfl(cq, kWave - 1, kWave);
+        }
+        if (__ballot(bl)) bad = bad || lane == src;
+    }
+    if (bad) atomicOr(err, kErrBadCsr);
 }
+
+constexpr int kLoopRowsPerWG = 256;   // rows per workgroup of the helper kernels
 
 // Column compression of every B row (set = col >> 5, mask bit = col & 31),
 // padded layout: the words of row k start at B's entry offset of row k.
@@ -513,7 +540,7 @@ void launch_validate(const Batch &b, int which, const int64_t *nnz_tab, uint32_t
     int n = which == 0 ? b.na : b.nb;
     if (n <= 0) return;
     ProfScope ps("validate", s);
-    hipLaunchKernelGGL(k_validate, dim3(nblk(n, kLoopRowsPerWG)), dim3(kWG), 0, s, b, which, nnz_tab, err);
+    hipLaunchKernelGGL(k_validate, dim3(nblk(n, kWG)), dim3(kWG), 0, s, b, which, nnz_tab, err);
 }
 
 void launch_compress(const Batch &b, hipStream_t s)

@@ -395,12 +395,19 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
             const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
             MLS_G int32_t *__restrict__ cci = gpw(get_prob(b, t).cci);
             const uint32_t set = cur.w.x;
-            const int pc = lane < n ? __popc(cur.w.y) : 0;
+            // set < 2^26 (columns < 2^31) and a popcount <= 32 share one word:
+            // set << 6 | popcount, so one lane read carries both, and
+            // key_f < set << 6 exactly when set_f < set. Lanes at or past n
+            // carry popcount 0, so the loop may run to a multiple of 4.
+            const uint32_t base = set << 6;
+            const uint32_t key = base | (uint32_t)(lane < n ? __popc(cur.w.y) : 0);
             int off = 0;
-            for (int f = 0; f < n; ++f) {
-                const uint32_t sf = (uint32_t)__builtin_amdgcn_readlane((int)set, f);
-                const int pf = __builtin_amdgcn_readlane(pc, f);
-                off += sf < set ? pf : 0;
+            for (int f = 0; f < n; f += 4) {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const uint32_t kf = (uint32_t)__builtin_amdgcn_readlane((int)key, f + d);
+                    off += kf < base ? (int)(kf & 63u) : 0;
+                }
             }
             if (lane < n) {
                 uint32_t m = cur.w.y;

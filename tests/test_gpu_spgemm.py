@@ -182,6 +182,35 @@ def test_device_validation(bad):
         mls.symbolic(mls.DeviceCsr.from_host(Abad), mls.DeviceCsr.from_host(B))
 
 
+@pytest.mark.parametrize("side", ["A", "B"])
+@pytest.mark.parametrize("pos", [0, 63, 64, 130, 199])
+@pytest.mark.parametrize("bad", ["unsorted", "duplicate", "out_of_range"])
+def test_device_validation_long_rows(side, pos, bad):
+    # rows of 200 entries take the wave-cooperative check; the planted error
+    # sits at chunk starts, chunk ends and the row's last entry
+    M = wide_rows(40, 500, 200, 7)
+    rp, ci = M.row_ptr.copy(), M.col_idx.copy()
+    s = int(rp[17])
+    q = s + pos
+    if bad == "unsorted":
+        a, b2 = (q, q + 1) if pos < 199 else (q - 1, q)
+        ci[a], ci[b2] = ci[b2], ci[a]
+    elif bad == "duplicate":
+        if pos < 199:
+            ci[q + 1] = ci[q]
+        else:
+            ci[q] = ci[q - 1]
+    else:
+        ci[q] = 500 if pos == 199 else -3
+    Mbad = synth.Csr(M.nrows, M.ncols, rp, ci, M.values)
+    if side == "A":
+        X, Y = Mbad, synth.poisson_csr(500, 30, 4.0, 1)
+    else:
+        X, Y = synth.poisson_csr(30, 40, 4.0, 2), Mbad
+    with pytest.raises(mls.SpgemmError, match="BAD_CSR"):
+        mls.symbolic(mls.DeviceCsr.from_host(X), mls.DeviceCsr.from_host(Y))
+
+
 def test_dimension_mismatch():
     A = synth.poisson_csr(10, 20, 4.0, 2)
     B = synth.poisson_csr(21, 30, 4.0, 1)
