@@ -20,6 +20,7 @@
 namespace mls {
 
 constexpr uint32_t kEmptyKey = 0xffffffffu;
+constexpr int kSymBatch = 12;  // words of one B_k row loaded before they are inserted
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -148,13 +149,13 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
                 int kl = k - k_lo;
                 const MLS_G u32x2 *w = bw + (brp[kl] - b_off);
                 const int nw = bwc[kl];
-                for (int x = 0; x < nw; x += 4) {
-                    u32x2 wd[4];
+                for (int x = 0; x < nw; x += kSymBatch) {
+                    u32x2 wd[kSymBatch];
 #pragma unroll
-                    for (int d = 0; d < 4; ++d)
+                    for (int d = 0; d < kSymBatch; ++d)
                         if (x + d < nw) wd[d] = w[x + d];
 #pragma unroll
-                    for (int d = 0; d < 4; ++d)
+                    for (int d = 0; d < kSymBatch; ++d)
                         if (x + d < nw) set_insert(key, msk, logcap, wd[d].x, wd[d].y, sc.err);
                 }
             }
