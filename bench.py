@@ -320,7 +320,40 @@ def bench_backward(torch, mls, synth):
     return res
 
 
-def bench_tc(torch, mls, synth, scale):
+def tc_word_model(n, lrp, lci):
+    """Compressed-word accounting of (L * comp(L)) o L from L's structure:
+    words of each row (distinct col >> 5), the word operations (for every
+    entry (i, k) of L, the words of row k), and the model bytes (L streamed,
+    row i's own words, 8 bytes per gathered word, 8 bytes per row written)."""
+    sets = lci.astype(np.int64) >> 5
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(lrp))
+    new_word = np.ones(len(lci), dtype=bool)
+    if len(lci):
+        new_word[1:] = (sets[1:] != sets[:-1]) | (rows[1:] != rows[:-1])
+    words = np.bincount(rows[new_word], minlength=n).astype(np.int64)
+    wordops = int(words[lci].sum())
+    uncompressed = int(np.diff(lrp).astype(np.int64)[lci].sum())
+    model = 4 * (n + 1) + 4 * len(lci) + 8 * int(words.sum()) + 8 * wordops + 8 * n
+    return words, wordops, uncompressed, model
+
+
+def tc_cpu_baseline(n, lrp, lci):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    L = synth_csr(n, lrp, lci)
+    t0 = time.perf_counter()
+    oracle.tc_count(L, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(dt * 1e3, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"the whole graph ({n} rows of L), flag-stamping oracle in C with OpenMP, {dt:.2f} s"}
+
+
+def synth_csr(n, lrp, lci):
+    import synth
+    return synth.Csr(n, n, lrp, lci, None)
+
+
+def bench_tc(torch, mls, synth, scale, with_cpu):
     log(f"generating R-MAT scale {scale}")
     G = synth.rmat_graph(scale, 16, seed=3)
     t0 = time.perf_counter()
@@ -330,12 +363,33 @@ def bench_tc(torch, mls, synth, scale):
     ws = mls.Workspace()
     mls.triangle_count(L, ws)
     med, best = timed(torch, lambda: mls.triangle_count(L, ws), 5)
+    mls.lib.spgemm_profile_reset()
+    mls.set_option(mls._abi.OPT_PROFILE, 1)
+    for _ in range(3):
+        mls.triangle_count(L, ws)
+    torch.cuda.synchronize()
+    mls.set_option(mls._abi.OPT_PROFILE, 0)
+    prof = profile_table(mls)
     _, total = mls.triangle_count(L, ws)
-    return {"metric": "triangle counting time (masked L*compressed(L)), R-MAT", "value": round(med, 3), "unit": "ms",
-            "higher_is_better": False, "n_gpus": 1, "best_ms": round(best, 3), "triangles": int(total),
-            "config": {"workload": f"R-MAT scale {scale}, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 3",
-                       "vertices": n, "edges": int(len(lci))},
-            "host_preprocessing_s": round(t_pre, 2), "dtype": "int64", "data": "synthetic"}
+    words, wordops, unc, model = tc_word_model(n, np.asarray(lrp), np.asarray(lci))
+    lds = {k: v for k, v in prof.items() if k.startswith("tc_lds")}
+    dom_name, (dc, dt) = max(lds.items(), key=lambda kv: kv[1][1])
+    tc_ms = sum(t for k, (c, t) in prof.items() if k.startswith("tc_")) / 3
+    achieved = model / (tc_ms * 1e-3) / 1e9
+    res = {"metric": "triangle counting time (masked L*compressed(L)), R-MAT", "value": round(med, 3), "unit": "ms",
+           "higher_is_better": False, "n_gpus": 1, "best_ms": round(best, 3), "triangles": int(total),
+           "config": {"workload": f"R-MAT scale {scale}, edge factor 16, a=.57 b=.19 c=.19 d=.05, seed 3",
+                      "vertices": n, "edges": int(len(lci)), "words_L": int(words.sum()),
+                      "word_ops": wordops, "uncompressed_ops": unc},
+           "word_ops_per_s": round(wordops / (med * 1e-3), 1),
+           "roofline": {"bound": "hbm", "kernels": "tc_*", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "model_bytes": model,
+                        "kernels_ms": round(tc_ms, 4), "dominant": dom_name},
+           "kernels": {k: {"calls": c, "avg_ms": round(t / c, 4)} for k, (c, t) in sorted(prof.items())},
+           "host_preprocessing_s": round(t_pre, 2), "dtype": "int64", "data": "synthetic"}
+    if with_cpu:
+        res["cpu_baseline"] = tc_cpu_baseline(n, np.asarray(lrp), np.asarray(lci))
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -369,7 +423,7 @@ def main():
         torch.cuda.synchronize()
         del x, y
     if args.workload == "tc":
-        print(json.dumps(bench_tc(torch, mls, synth, args.tc_scale)), flush=True)
+        print(json.dumps(bench_tc(torch, mls, synth, args.tc_scale, not args.quick)), flush=True)
         return
 
     n = args.n
@@ -436,6 +490,7 @@ def main():
     compulsory = csr_bytes(A.nrows, A.nnz) * 2 + csr_bytes(A.nrows, nnzC)
     achieved = model / (dom_ms * 1e-3) / 1e9
     kernels = {k: {"calls": c, "avg_ms": round(t / c, 4)} for k, (c, t) in sorted(prof.items())}
+    traffic = committed_traffic() if n == 128 else None
     sym_ms = sum(t for k, (c, t) in prof.items() if k.startswith("sym_")) / args.steps
 
     result = {
@@ -459,7 +514,9 @@ def main():
         "symbolic_kernels_ms": round(sym_ms, 4),
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": committed_traffic() if n == 128 else None,
+                     "traffic": traffic,
+                     "traffic_frac": (round(traffic / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if traffic else None),
                      "kernel_avg_ms": round(dom_ms, 4), "algorithmic_bytes": model,
                      "compulsory_bytes": compulsory,
                      "compulsory_frac": round(compulsory / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},

@@ -34,13 +34,19 @@ constexpr int nw_tc(int row_bytes, int rows_per_wave)
     return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
 }
 
-template <int G, int CAP>
+// LDS per row: the own-word table (key, mask) and the staged entries
+constexpr int tc_row_bytes(int CAP, int G) { return CAP * 8 + G * 12 + 4; }
+
+template <int G, int CAP, int PW, int PP>
 __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int64_t *counts)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_tc(CAP * 8, W);
+    constexpr int NW = nw_tc(tc_row_bytes(CAP, G), W);
     __shared__ uint32_t s_key[NW * W * CAP];
     __shared__ uint32_t s_msk[NW * W * CAP];
+    __shared__ int s_poff[NW * W * (G + 1)];   // first piece of each staged entry, then the total
+    __shared__ int s_st[NW * W * G];           // word offset of each staged entry's row
+    __shared__ int s_nk[NW * W * G];           // its word count
 
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;
@@ -49,6 +55,9 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
     const int rs = wave * W + slot;
     uint32_t *key = s_key + rs * CAP;
     uint32_t *msk = s_msk + rs * CAP;
+    int *poff = s_poff + rs * (G + 1);
+    int *pst = s_st + rs * G;
+    int *pnk = s_nk + rs * G;
 
     const Prob P = b.p0;
     const MLS_G int32_t *__restrict__ lrp = gp(P.arp);
@@ -90,22 +99,71 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
         }
         tc_sync();
         uint32_t cnt = 0;
-        if (active) {
-            for (int p = ps + lane; p < pe; p += G) {
-                const int k = lci[p];
-                const MLS_G u32x2 *wk = bw + lrp[k];
-                const int nk = bwc[k];
-                for (int x = 0; x < nk; ++x) {
-                    u32x2 wd = wk[x];
-                    uint32_t h = hslot(wd.x, logcap);
-                    for (uint32_t probe = 0; probe <= cmask; ++probe) {
-                        uint32_t kk = key[h];
-                        if (kk == wd.x) { cnt += __popc(wd.y & msk[h]); break; }
-                        if (kk == kTcEmpty) break;
-                        h = (h + 1u) & cmask;
+        // Entries k of row i are staged G at a time; the words of row k of
+        // comp(L) are cut into pieces of PW words, and the pieces of the
+        // chunk are dealt round-robin to the lanes, so that one long row of L
+        // does not hold up the group. A piece's entry is found by binary
+        // search over the staged first-piece offsets. Pieces hold PW words; PP
+        // pieces per lane are in flight at once.
+        for (int pc = ps; pc < pe; pc += G) {   // ps == pe for inactive rows
+            int st = 0, nk = 0;
+            if (pc + lane < pe) {
+                const int k = lci[pc + lane];
+                st = lrp[k];
+                nk = bwc[k];
+            }
+            const int np = (nk + PW - 1) / PW;
+            int incl = np;
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) {
+                const int y = __shfl_up(incl, o, G);
+                if (lane >= o) incl += y;
+            }
+            const int npieces = __shfl(incl, G - 1, G);
+            poff[lane] = incl - np;
+            pst[lane] = st;
+            pnk[lane] = nk;
+            if (lane == 0) poff[G] = npieces;
+            tc_sync();
+            for (int q0 = lane; q0 < npieces; q0 += G * PP) {
+                // PP pieces per round: their entries are found, their words loaded,
+                // and only then looked up
+                u32x2 wd[PP][PW];
+                int len[PP];
+#pragma unroll
+                for (int r = 0; r < PP; ++r) {
+                    const int q = q0 + r * G;
+                    len[r] = 0;
+                    if (q < npieces) {
+                        int lo = 0, hi = G - 1;   // largest e with poff[e] <= q
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (poff[mid] <= q) lo = mid; else hi = mid - 1;
+                        }
+                        const int first = (q - poff[lo]) * PW;
+                        len[r] = min(PW, pnk[lo] - first);
+                        const MLS_G u32x2 *wk = bw + pst[lo] + first;
+#pragma unroll
+                        for (int d = 0; d < PW; ++d)
+                            if (d < len[r]) wd[r][d] = wk[d];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < PP; ++r) {
+#pragma unroll
+                    for (int d = 0; d < PW; ++d) {
+                        if (d >= len[r]) continue;
+                        uint32_t h = hslot(wd[r][d].x, logcap);
+                        for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                            uint32_t kk = key[h];
+                            if (kk == wd[r][d].x) { cnt += __popc(wd[r][d].y & msk[h]); break; }
+                            if (kk == kTcEmpty) break;
+                            h = (h + 1u) & cmask;
+                        }
                     }
                 }
             }
+            tc_sync();
         }
         int64_t c = group_sum<G>((int64_t)cnt);
         if (active && lane == 0) gpw(counts)[i] = c;
@@ -213,16 +271,16 @@ static int tc_grid(K kernel, int threads)
     return cus * per_cu;
 }
 
-template <int G, int CAP>
+template <int G, int CAP, int P, int PP>
 static void launch_tc_class(const Batch &b, const Sched &sc, int bin, int64_t *counts, hipStream_t s)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_tc(CAP * 8, W);
-    static int grid = tc_grid(k_tc_lds<G, CAP>, NW * kWave);
+    constexpr int NW = nw_tc(tc_row_bytes(CAP, G), W);
+    static int grid = tc_grid(k_tc_lds<G, CAP, P, PP>, NW * kWave);
     static char name[64];
     if (!name[0]) snprintf(name, sizeof(name), "tc_lds_G%d_C%d", G, CAP);
     ProfScope ps(name, s);
-    hipLaunchKernelGGL((k_tc_lds<G, CAP>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, counts);
+    hipLaunchKernelGGL((k_tc_lds<G, CAP, P, PP>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, counts);
 }
 
 void launch_tc_bin(const Batch &b, const Sched &sc, int force_spill, hipStream_t s)
@@ -240,9 +298,10 @@ void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long l
                int spill_slots, int64_t spill_words, hipStream_t s)
 {
     if (b.na <= 0) return;
-    launch_tc_class<16, kFillCap[0]>(b, sc, 0, counts, s);
-    launch_tc_class<64, kFillCap[1]>(b, sc, 1, counts, s);
-    launch_tc_class<64, kFillCap[2]>(b, sc, 2, counts, s);
+    // lanes per row, words per piece, pieces in flight per lane: measured on R-MAT
+    launch_tc_class<32, kFillCap[0], 8, 1>(b, sc, 0, counts, s);
+    launch_tc_class<64, kFillCap[1], 8, 1>(b, sc, 1, counts, s);
+    launch_tc_class<64, kFillCap[2], 8, 1>(b, sc, 2, counts, s);
     {
         ProfScope ps("tc_spill", s);
         hipLaunchKernelGGL(k_tc_spill, dim3(spill_slots), dim3(kWG), 0, s, b, sc, counts, spill_bitmaps, spill_words);
