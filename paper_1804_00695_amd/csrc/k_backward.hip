@@ -223,15 +223,16 @@ void launch_backward(const Batch &b, const Sched &sc, const double *wval, double
 {
     (void)wval;
     if (b.na <= 0) return;
+    launch_bwd_class<8, kFillCap[0]>(b, sc, 0, dA, dB, s);
     switch (G) {
-    case 8: launch_bwd_class<8, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
-    case 16: launch_bwd_class<16, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
-    case 64: launch_bwd_class<64, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
-    default: launch_bwd_class<32, kFillCap[0]>(b, sc, 0, dA, dB, s); break;
+    case 8: launch_bwd_class<8, kFillCap[1]>(b, sc, 1, dA, dB, s); break;
+    case 16: launch_bwd_class<16, kFillCap[1]>(b, sc, 1, dA, dB, s); break;
+    case 64: launch_bwd_class<64, kFillCap[1]>(b, sc, 1, dA, dB, s); break;
+    default: launch_bwd_class<32, kFillCap[1]>(b, sc, 1, dA, dB, s); break;
     }
-    if (G >= 64) launch_bwd_class<64, kFillCap[1]>(b, sc, 1, dA, dB, s);
-    else launch_bwd_class<32, kFillCap[1]>(b, sc, 1, dA, dB, s);
-    launch_bwd_class<64, kFillCap[2]>(b, sc, 2, dA, dB, s);
+    if (G >= 64) launch_bwd_class<64, kFillCap[2]>(b, sc, 2, dA, dB, s);
+    else launch_bwd_class<32, kFillCap[2]>(b, sc, 2, dA, dB, s);
+    launch_bwd_class<64, kFillCap[3]>(b, sc, 3, dA, dB, s);
     static int spill_grid = device_cu_count();
     ProfScope ps("bwd_spill", s);
     hipLaunchKernelGGL(k_bwd_spill, dim3(spill_grid), dim3(kWG), 0, s, b, sc, dA, dB);

@@ -52,8 +52,8 @@ constexpr int nw_num(int row_bytes, int rows_per_wave)
 // column range excludes the all-ones column field.
 template <int CAP>
 struct PackBits {
-    static constexpr int PB = (CAP == 256) ? 7 : (CAP == 1024 ? 9 : 11);
-    static_assert(CAP == 256 || CAP == 1024 || CAP == 4096, "table class");
+    static constexpr int PB = CAP == 64 ? 5 : (CAP == 256 ? 7 : (CAP == 1024 ? 9 : 11));
+    static_assert(CAP == 64 || CAP == 256 || CAP == 1024 || CAP == 4096, "table class");
     static constexpr uint32_t kMaxCols = (1u << (32 - PB)) - 1u;   // columns < this fit
 };
 
@@ -390,15 +390,16 @@ static void launch_num_class(const Batch &b, const Sched &sc, int bin, hipStream
 void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s)
 {
     if (b.na <= 0) return;
+    launch_num_class<8, kFillCap[0]>(b, sc, 0, s);
     switch (G) {
-    case 8: launch_num_class<8, kFillCap[0]>(b, sc, 0, s); break;
-    case 16: launch_num_class<16, kFillCap[0]>(b, sc, 0, s); break;
-    case 64: launch_num_class<64, kFillCap[0]>(b, sc, 0, s); break;
-    default: launch_num_class<32, kFillCap[0]>(b, sc, 0, s); break;
+    case 8: launch_num_class<8, kFillCap[1]>(b, sc, 1, s); break;
+    case 16: launch_num_class<16, kFillCap[1]>(b, sc, 1, s); break;
+    case 64: launch_num_class<64, kFillCap[1]>(b, sc, 1, s); break;
+    default: launch_num_class<32, kFillCap[1]>(b, sc, 1, s); break;
     }
-    if (G >= 64) launch_num_class<64, kFillCap[1]>(b, sc, 1, s);
-    else launch_num_class<32, kFillCap[1]>(b, sc, 1, s);
-    launch_num_class<64, kFillCap[2]>(b, sc, 2, s);
+    if (G >= 64) launch_num_class<64, kFillCap[2]>(b, sc, 2, s);
+    else launch_num_class<32, kFillCap[2]>(b, sc, 2, s);
+    launch_num_class<64, kFillCap[3]>(b, sc, 3, s);
     static int spill_grid = device_cu_count();
     ProfScope ps("num_spill", s);
     hipLaunchKernelGGL(k_num_spill, dim3(spill_grid), dim3(kWG), 0, s, b, sc);

@@ -229,10 +229,10 @@ __device__ __forceinline__ int class_of(int mode, int64_t size, int force_spill)
     if (size == 0) return kBinEmpty;
     if (force_spill) return kBinSpill;
     if (mode == kModeCount) {
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < kNumClasses; ++c)
             if (size <= kCountCap[c]) return c;
     } else {
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < kNumClasses; ++c)
             if (size <= kFillCap[c] / 2) return c;
     }
     return kBinSpill;

@@ -352,29 +352,27 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
     }
 }
 
-// Fill pass from the count pass's scratch: one wave per row, lane e holding
-// word e (a row keeps at most kScratchWords = 64 words). A word's output
-// offset is the popcount sum of the words with smaller sets, accumulated from
-// lane reads (no LDS); its bits then expand into ascending columns. The loads
-// of the next row (its word count, all 64 scratch slots, its C row bounds)
-// are issued before the current row's stores, so that waiting for them never
-// waits for those stores. Rows without scratch words (scnt < 0) are left to
-// the recomputing fill kernels.
+// Fill pass from the count pass's scratch: lane e holds word e of a row (a
+// row keeps at most kScratchWords = 64 words). A word's output offset is the
+// popcount sum of the words with smaller sets, accumulated from lane reads
+// (no LDS); its bits then expand into ascending columns. Rows without scratch
+// words (scnt < 0) are left to the recomputing fill kernels.
 static_assert(kScratchWords == kWave, "one scratch word per lane");
+constexpr int kExpandSmall = 16;   // rows with at most this many words take the 16-lane kernel
 
 struct ExpandRow {
-    int n, cs, ce;
+    int cs, ce;
     u32x2 w;
 };
 
-__device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc, int g, int lane)
+// Scratch words (lane < n) and C row bounds of global row g.
+__device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc, int g, int n, int lane)
 {
     ExpandRow r;
-    r.n = -1; r.cs = 0; r.ce = 0;
+    r.cs = 0; r.ce = 0;
     r.w.x = 0u; r.w.y = 0u;
-    if (g >= b.na) return r;
-    r.n = gp(sc.scnt)[g];
-    r.w = ((const MLS_G u32x2 *)sc.scr)[(int64_t)g * kScratchWords + lane];
+    if (g < 0) return r;
+    if (lane < n) r.w = ((const MLS_G u32x2 *)sc.scr)[(int64_t)g * kScratchWords + lane];
     const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
     const Prob P = get_prob(b, t);
     const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
@@ -383,16 +381,34 @@ __device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc
     return r;
 }
 
+// Rows of more than kExpandSmall words: a wave reads the word counts of 64
+// consecutive rows, then takes the large ones one at a time; the next large
+// row's words are loaded while the current one is ranked and written.
 __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
 {
     const int lane = threadIdx.x & 63;
     const int nw = (int)gridDim.x * (kWG / kWave);
-    int g = (int)((blockIdx.x * kWG + threadIdx.x) >> 6);
-    ExpandRow cur = expand_load(b, sc, g, lane);
-    for (; g < b.na; g += nw) {
-        const ExpandRow nxt = expand_load(b, sc, g + nw, lane);
-        const int n = __builtin_amdgcn_readfirstlane(cur.n);   // uniform: one row per wave
-        if (n > 0) {
+    const int w0 = (int)((blockIdx.x * kWG + threadIdx.x) >> 6);
+    const MLS_G int32_t *scnt = gp(sc.scnt);
+    for (int base = w0 * kWave; base < b.na; base += nw * kWave) {
+        const int gl = base + lane;
+        const int nl = gl < b.na ? scnt[gl] : 0;
+        unsigned long long big = __ballot(nl > kExpandSmall);
+        if (!big) continue;
+        int r = __ffsll((long long)big) - 1;
+        big &= big - 1ull;
+        int n = __builtin_amdgcn_readlane(nl, r);
+        ExpandRow cur = expand_load(b, sc, base + r, n, lane);
+        for (;;) {
+            // prefetch the next large row of this chunk
+            int rn = -1, nn = 0;
+            if (big) {
+                rn = __ffsll((long long)big) - 1;
+                big &= big - 1ull;
+                nn = __builtin_amdgcn_readlane(nl, rn);
+            }
+            const ExpandRow nxt = expand_load(b, sc, rn >= 0 ? base + rn : -1, nn, lane);
+            const int g = base + r;
             const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
             MLS_G int32_t *__restrict__ cci = gpw(get_prob(b, t).cci);
             const uint32_t set = cur.w.x;
@@ -400,14 +416,14 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
             // set << 6 | popcount, so one lane read carries both, and
             // key_f < set << 6 exactly when set_f < set. Lanes at or past n
             // carry popcount 0, so the loop may run to a multiple of 4.
-            const uint32_t base = set << 6;
-            const uint32_t key = base | (uint32_t)(lane < n ? __popc(cur.w.y) : 0);
+            const uint32_t kbase = set << 6;
+            const uint32_t key = kbase | (uint32_t)(lane < n ? __popc(cur.w.y) : 0);
             int off = 0;
             for (int f = 0; f < n; f += 4) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     const uint32_t kf = (uint32_t)__builtin_amdgcn_readlane((int)key, f + d);
-                    off += kf < base ? (int)(kf & 63u) : 0;
+                    off += kf < kbase ? (int)(kf & 63u) : 0;
                 }
             }
             if (lane < n) {
@@ -421,8 +437,59 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
                     m &= m - 1u;
                 }
             }
+            if (rn < 0) break;
+            r = rn;
+            n = nn;
+            cur = nxt;
         }
-        cur = nxt;
+    }
+}
+
+// Rows of at most kExpandSmall words: 16 lanes per row, four rows per wave;
+// word f of the row is read from lane f of the group by a lane shuffle.
+__global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
+{
+    constexpr int G = kExpandSmall;
+    const int lane = threadIdx.x % G;
+    const int rows_per_grid = (int)gridDim.x * (kWG / G);
+    const MLS_G int32_t *scnt = gp(sc.scnt);
+    const MLS_G u32x2 *scr = (const MLS_G u32x2 *)sc.scr;
+    const int first = (int)(blockIdx.x * (kWG / G) + threadIdx.x / G);
+    const int na = b.na;
+    // every group of a wave runs the same number of iterations (the shuffles need them all)
+    const int nit = (na - (int)(blockIdx.x * (kWG / G)) + rows_per_grid - 1) / rows_per_grid;
+    for (int it = 0; it < nit; ++it) {
+        const int g = first + it * rows_per_grid;
+        int n = g < na ? scnt[g] : 0;
+        if (n > G) n = 0;   // larger rows belong to the wave-per-row kernel
+        u32x2 w;
+        w.x = 0u; w.y = 0u;
+        if (lane < n) w = scr[(int64_t)g * kScratchWords + lane];
+        const uint32_t base = w.x << 6;
+        const uint32_t key = base | (uint32_t)(lane < n ? __popc(w.y) : 0);
+        int off = 0;
+#pragma unroll
+        for (int f = 0; f < G; ++f) {
+            const uint32_t kf = (uint32_t)__shfl((int)key, f, G);
+            off += kf < base ? (int)(kf & 63u) : 0;
+        }
+        if (lane < n) {
+            const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+            const Prob P = get_prob(b, t);
+            const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+            const int cs = gp(P.crp)[i] - P.c_off;
+            const int ce = gp(P.crp)[i + 1] - P.c_off;
+            MLS_G int32_t *__restrict__ cci = gpw(P.cci);
+            uint32_t m = w.y;
+            int pos = cs + off;
+            while (m) {
+                const int bit = __ffs(m) - 1;
+                if (pos < ce) cci[pos] = (int32_t)(w.x * 32u + (uint32_t)bit);
+                else atomicOr(sc.err, kErrStructure);
+                ++pos;
+                m &= m - 1u;
+            }
+        }
     }
 }
 
@@ -430,6 +497,10 @@ void launch_sym_expand(const Batch &b, const Sched &sc, hipStream_t s)
 {
     if (b.na <= 0 || !sc.scr) return;
     static int cus = device_cu_count();
+    {
+        ProfScope ps("sym_expand_small", s);
+        hipLaunchKernelGGL(k_sym_expand_small, dim3(cus * 8), dim3(kWG), 0, s, b, sc);
+    }
     ProfScope ps("sym_expand", s);
     hipLaunchKernelGGL(k_sym_expand, dim3(cus * 8), dim3(kWG), 0, s, b, sc);
 }
@@ -464,15 +535,17 @@ static void launch_sym_all(const Batch &b, const Sched &sc, int G, hipStream_t s
     constexpr int C0 = FILL ? kFillCap[0] : kCountCap[0];
     constexpr int C1 = FILL ? kFillCap[1] : kCountCap[1];
     constexpr int C2 = FILL ? kFillCap[2] : kCountCap[2];
+    constexpr int C3 = FILL ? kFillCap[3] : kCountCap[3];
+    launch_sym_class<8, C0, FILL>(b, sc, 0, s);
     switch (G) {
-    case 8: launch_sym_class<8, C0, FILL>(b, sc, 0, s); break;
-    case 16: launch_sym_class<16, C0, FILL>(b, sc, 0, s); break;
-    case 64: launch_sym_class<64, C0, FILL>(b, sc, 0, s); break;
-    default: launch_sym_class<32, C0, FILL>(b, sc, 0, s); break;
+    case 8: launch_sym_class<8, C1, FILL>(b, sc, 1, s); break;
+    case 16: launch_sym_class<16, C1, FILL>(b, sc, 1, s); break;
+    case 64: launch_sym_class<64, C1, FILL>(b, sc, 1, s); break;
+    default: launch_sym_class<32, C1, FILL>(b, sc, 1, s); break;
     }
-    if (G >= 64) launch_sym_class<64, C1, FILL>(b, sc, 1, s);
-    else launch_sym_class<32, C1, FILL>(b, sc, 1, s);
-    launch_sym_class<64, C2, FILL>(b, sc, 2, s);
+    if (G >= 64) launch_sym_class<64, C2, FILL>(b, sc, 2, s);
+    else launch_sym_class<32, C2, FILL>(b, sc, 2, s);
+    launch_sym_class<64, C3, FILL>(b, sc, 3, s);
 }
 
 void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, uint32_t *spill_bitmaps, int spill_slots,

@@ -237,7 +237,11 @@ __global__ __launch_bounds__(kWG) void k_tc_bin(Batch b, Sched sc, int force_spi
         int c;
         if (len == 0) c = kBinEmpty;
         else if (force_spill) c = kBinSpill;
-        else c = size <= kFillCap[0] / 2 ? 0 : (size <= kFillCap[1] / 2 ? 1 : (size <= kFillCap[2] / 2 ? 2 : kBinSpill));
+        else {
+            c = kBinSpill;
+            for (int x = kNumClasses - 1; x >= 0; --x)
+                if (size <= kFillCap[x] / 2) c = x;
+        }
         gpw(sc.val)[i] = size;
         gpw(sc.cls)[i] = (uint8_t)c;
         atomicAdd(&cnt[c], 1);
@@ -299,9 +303,10 @@ void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long l
 {
     if (b.na <= 0) return;
     // lanes per row, words per piece, pieces in flight per lane: measured on R-MAT
-    launch_tc_class<32, kFillCap[0], 8, 1>(b, sc, 0, counts, s);
-    launch_tc_class<64, kFillCap[1], 8, 1>(b, sc, 1, counts, s);
+    launch_tc_class<16, kFillCap[0], 8, 1>(b, sc, 0, counts, s);
+    launch_tc_class<32, kFillCap[1], 8, 1>(b, sc, 1, counts, s);
     launch_tc_class<64, kFillCap[2], 8, 1>(b, sc, 2, counts, s);
+    launch_tc_class<64, kFillCap[3], 8, 1>(b, sc, 3, counts, s);
     {
         ProfScope ps("tc_spill", s);
         hipLaunchKernelGGL(k_tc_spill, dim3(spill_slots), dim3(kWG), 0, s, b, sc, counts, spill_bitmaps, spill_words);

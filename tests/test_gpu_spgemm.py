@@ -134,11 +134,11 @@ def with_last_column(B):
 
 @pytest.mark.parametrize("ncols", [(1 << 21) - 1, 1 << 21, (1 << 23) - 1, 1 << 23, (1 << 25) - 1, 1 << 25])
 def test_packed_table_column_limits(ncols):
-    # row sizes in all three LDS classes; the packed slots hold column indices
-    # below 2^21 - 1, 2^23 - 1 and 2^25 - 1 for the classes of 4096, 1024 and
-    # 256 slots, and the wide slots take over from there
+    # row sizes in all four LDS classes; the packed slots hold column indices
+    # below 2^21 - 1, 2^23 - 1, 2^25 - 1 and 2^27 - 1 for the classes of 4096,
+    # 1024, 256 and 64 slots, and the wide slots take over from there
     B = with_last_column(synth.poisson_csr(3000, ncols, 6.0, 31))
-    for per_row, seed in ((10, 1), (60, 2), (200, 3)):
+    for per_row, seed in ((3, 4), (10, 1), (60, 2), (200, 3)):
         check(wide_rows(24, 3000, per_row, seed), B)
 
 
