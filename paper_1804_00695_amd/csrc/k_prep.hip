@@ -25,25 +25,14 @@ __global__ void k_fill_f64(double *p, double v, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
-// Row-cooperative helpers: 32 lanes share a row and read its entries in
-// coalesced chunks of 32; 8 rows per 256-thread workgroup.
-
-constexpr int kRowG = 32;
-constexpr int kRowsPerWG = kWG / kRowG;
-
-__device__ __forceinline__ uint32_t group_ballot(bool pred, int slot_in_wave)
-{
-    // 64-bit wave ballot, cut to the 32 lanes of this row group
-    unsigned long long b = __ballot(pred);
-    return (uint32_t)(b >> (32 * slot_in_wave));
-}
+// Per-row helpers: one thread per short row, the whole wave per long row.
 
 // CSR checks over the A rows (which = 0) or B rows (which = 1) of a batch:
 // row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, columns in range and
 // strictly increasing. Column indices outside [0, nnz) are never read.
 // One thread per row walks rows of up to kShortRow entries; the wave checks
 // longer rows together, one at a time, 64 entries per step.
-constexpr int kShortRow = 64;
+constexpr int kShortRow = 16;
 
 __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
 {
@@ -114,60 +103,102 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
     if (bad) atomicOr(err, kErrBadCsr);
 }
 
-constexpr int kLoopRowsPerWG = 256;   // rows per workgroup of the helper kernels
-
 // Column compression of every B row (set = col >> 5, mask bit = col & 31),
 // padded layout: the words of row k start at B's entry offset of row k.
-// Chunks of 32 entries: a lane starts a word where its set differs from the
-// previous entry's; masks are OR-ed in LDS; the last word of a chunk stays
-// open (it may continue in the next chunk).
-__device__ __forceinline__ void compress_row(const Batch &b, int g, uint32_t *wset, uint32_t *wmsk)
+// One thread per row walks rows of up to kCompressShort entries; the wave
+// takes longer rows together, 64 entries per step: a lane starts a word where its
+// set differs from the previous entry's, masks are OR-ed in LDS, and the last
+// word of a step stays open (it may continue in the next step).
+constexpr int kCompressShort = 16;   // longest row a single thread compresses (measured)
+
+__global__ __launch_bounds__(kWG) void k_compress(Batch b)
 {
-    const int slot = threadIdx.x / kRowG, lane = threadIdx.x % kRowG;
-    const int wslot = slot & 1;   // which half of the 64-lane wave
-    const bool row_ok = g < b.nb;
-    int t = 0, k = 0;
-    Prob P = b.p0;
-    if (row_ok) {
-        t = b.nprob == 1 ? 0 : find_prob(b.bbase, b.nprob, g);
-        P = get_prob(b, t);
-        k = g - (b.nprob == 1 ? 0 : gp(b.bbase)[t]);
-    }
-    const int s = row_ok ? gp(P.brp)[k] - P.b_off : 0;
-    const int e = row_ok ? gp(P.brp)[k + 1] - P.b_off : 0;
-    const MLS_G int32_t *__restrict__ bci = gp(P.bci);
-    MLS_G u32x2 *__restrict__ out = (MLS_G u32x2 *)P.bw + s;
+    __shared__ uint32_t s_set[kWG / kWave][kWave + 1];
+    __shared__ uint32_t s_msk[kWG / kWave][kWave + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *wset = s_set[wave];
+    uint32_t *wmsk = s_msk[wave];
     const uint32_t kNone = 0xffffffffu;
-    uint32_t carry_set = kNone, carry_msk = 0;
-    (void)slot;
-    int nout = 0;
-    // every group of the wave runs the same number of chunks (shuffles need all lanes)
-    int len = e - s;
-    int maxlen = max(len, __shfl_xor(len, 32, kWave));
-    for (int c0 = 0; c0 < maxlen; c0 += kRowG) {
-        const int q = s + c0 + lane;
-        const bool valid = c0 + lane < len;
-        const uint32_t c = valid ? (uint32_t)bci[q] : 0u;
-        const uint32_t set = valid ? (c >> 5) : kNone;
-        uint32_t prev = __shfl_up(set, 1, kRowG);
-        if (lane == 0) prev = carry_set;
-        const bool head = valid && set != prev;
-        const uint32_t hm = group_ballot(head, wslot);
-        const int lw = __popc(hm & ((2u << lane) - 1u));   // 0 = continues the open word
-        wmsk[lane] = 0u;
-        if (lane == 0) wmsk[kRowG] = 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (valid) {
-            atomicOr(&wmsk[lw], 1u << (c & 31u));
-            if (head) wset[lw] = set;
+    const int g = blockIdx.x * kWG + threadIdx.x;
+    bool longrow = false;
+    const int32_t *ci_row = nullptr;
+    uint2 *out_row = nullptr;
+    int32_t *cnt_ptr = nullptr;
+    int len = 0;
+    if (g < b.nb) {
+        const int t = b.nprob == 1 ? 0 : find_prob(b.bbase, b.nprob, g);
+        const Prob P = get_prob(b, t);
+        const int k = g - (b.nprob == 1 ? 0 : gp(b.bbase)[t]);
+        const int s0 = gp(P.brp)[k] - P.b_off;
+        len = gp(P.brp)[k + 1] - P.b_off - s0;
+        ci_row = P.bci + s0;
+        out_row = P.bw + s0;
+        cnt_ptr = P.bwc + k;
+        if (len <= kCompressShort) {
+            const MLS_G int32_t *c = gp(ci_row);
+            MLS_G u32x2 *out = (MLS_G u32x2 *)out_row;
+            uint32_t cur = kNone, msk = 0;
+            int nout = 0;
+            for (int q0 = 0; q0 < len; q0 += 4) {
+                int cq[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) cq[d] = q0 + d < len ? c[q0 + d] : -1;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    if (cq[d] < 0) continue;
+                    const uint32_t set = (uint32_t)cq[d] >> 5;
+                    if (set != cur) {
+                        if (cur != kNone) { u32x2 w; w.x = cur; w.y = msk; out[nout++] = w; }
+                        cur = set;
+                        msk = 0;
+                    }
+                    msk |= 1u << (cq[d] & 31);
+                }
+            }
+            if (cur != kNone) { u32x2 w; w.x = cur; w.y = msk; out[nout++] = w; }
+            gpw(cnt_ptr)[0] = nout;
+        } else {
+            longrow = true;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const int nh = __popc(hm);
-        if (row_ok && c0 < len) {
+    }
+    unsigned long long lm = __ballot(longrow);
+    while (lm) {
+        const int src = __ffsll((long long)lm) - 1;
+        lm &= lm - 1ull;
+        const int n = __builtin_amdgcn_readlane(len, src);
+        auto rl64 = [&](const void *p) {
+            const uint64_t v = (uint64_t)p;
+            return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), src) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+        };
+        const MLS_G int32_t *c = (const MLS_G int32_t *)rl64(ci_row);
+        MLS_G u32x2 *out = (MLS_G u32x2 *)rl64(out_row);
+        int32_t *cp = (int32_t *)rl64(cnt_ptr);
+        uint32_t carry_set = kNone, carry_msk = 0;
+        int nout = 0;
+        for (int c0 = 0; c0 < n; c0 += kWave) {
+            const int q = c0 + lane;
+            const bool valid = q < n;
+            const uint32_t cv = valid ? (uint32_t)c[q] : 0u;
+            const uint32_t set = valid ? (cv >> 5) : kNone;
+            uint32_t prev = __shfl_up(set, 1, kWave);
+            if (lane == 0) prev = carry_set;
+            const bool head = valid && set != prev;
+            const unsigned long long hm = __ballot(head);
+            const int lw = __popcll(hm & ((2ull << lane) - 1ull));   // 0 = continues the open word
+            wmsk[lane] = 0u;
+            if (lane == 0) wmsk[kWave] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (valid) {
+                atomicOr(&wmsk[lw], 1u << (cv & 31u));
+                if (head) wset[lw] = set;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const int nh = __popcll(hm);
             // word 0 continues the open word; words 1..nh-1 are complete; word nh stays open
             if (nh > 0 && carry_set != kNone && lane == 0) {
                 u32x2 w; w.x = carry_set; w.y = carry_msk | wmsk[0];
@@ -178,40 +209,22 @@ __device__ __forceinline__ void compress_row(const Batch &b, int g, uint32_t *ws
                 u32x2 w; w.x = wset[lane]; w.y = wmsk[lane];
                 out[base_out + lane - 1] = w;
             }
-        }
-        if (nh > 0) {
-            nout += (carry_set != kNone ? 1 : 0) + nh - 1;
-            carry_set = wset[nh];
-            carry_msk = wmsk[nh];
-        } else {
-            carry_msk |= wmsk[0];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-    if (row_ok) {
-        if (carry_set != kNone) {
-            if (lane == 0) {
-                u32x2 w; w.x = carry_set; w.y = carry_msk;
-                out[nout] = w;
+            if (nh > 0) {
+                nout += (carry_set != kNone ? 1 : 0) + nh - 1;
+                carry_set = wset[nh];
+                carry_msk = wmsk[nh];
+            } else {
+                carry_msk |= wmsk[0];
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        if (carry_set != kNone) {
+            if (lane == 0) { u32x2 w; w.x = carry_set; w.y = carry_msk; out[nout] = w; }
             ++nout;
         }
-        if (lane == 0) gpw(P.bwc)[k] = nout;
-    }
-}
-
-__global__ __launch_bounds__(kWG) void k_compress(Batch b)
-{
-    __shared__ uint32_t s_set[kRowsPerWG][kRowG + 1];
-    __shared__ uint32_t s_msk[kRowsPerWG][kRowG + 1];
-    const int slot = threadIdx.x / kRowG;
-    // both row groups of a wave run the same rows count (they share ballots)
-    for (int r = slot & ~1; r < kLoopRowsPerWG; r += kRowsPerWG) {
-        const int g0 = blockIdx.x * kLoopRowsPerWG + r;
-        if (g0 >= b.nb) break;   // uniform per wave
-        compress_row(b, g0 + (slot & 1), s_set[slot], s_msk[slot]);
+        if (lane == 0) gpw(cp)[0] = nout;
     }
 }
 
@@ -547,7 +560,7 @@ void launch_compress(const Batch &b, hipStream_t s)
 {
     if (b.nb <= 0) return;
     ProfScope ps("compress", s);
-    hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kLoopRowsPerWG)), dim3(kWG), 0, s, b);
+    hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kWG)), dim3(kWG), 0, s, b);
 }
 
 void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsigned long long *total,

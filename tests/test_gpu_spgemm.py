@@ -161,6 +161,28 @@ def test_row_work_and_compress():
         assert np.array_equal(got[1::2], masks[rp[k]:rp[k + 1]])
 
 
+def test_compress_long_rows():
+    # rows longer than 64 entries take the wave-cooperative path: dense runs
+    # (words spanning the 64-entry steps), sparse rows, and lengths around 64
+    g = synth.rng(13)
+    rows = [np.arange(17, 217), np.sort(g.choice(5000, 300, replace=False)), np.arange(64), np.arange(30, 95),
+            np.array([4999]), np.sort(g.choice(5000, 63, replace=False)), np.arange(0, 5000, 7)[:400],
+            np.array([], dtype=np.int64), np.sort(g.choice(5000, 129, replace=False))]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    B = synth.Csr(len(rows), 5000, rp, np.concatenate(rows).astype(np.int32), None)
+    dB = mls.DeviceCsr.from_host(B)
+    words, count = mls.compress(dB)
+    words = words.cpu().numpy().view(np.uint32)
+    count = count.cpu().numpy()
+    crp, sets, masks = oracle.compress(B)
+    assert np.array_equal(count, np.diff(crp))
+    for k in range(B.nrows):
+        s0 = int(B.row_ptr[k])
+        got = words[2 * s0: 2 * (s0 + count[k])]
+        assert np.array_equal(got[0::2], sets[crp[k]:crp[k + 1]].view(np.uint32)), k
+        assert np.array_equal(got[1::2], masks[crp[k]:crp[k + 1]]), k
+
+
 @pytest.mark.parametrize("bad", ["unsorted", "duplicate", "out_of_range", "decreasing"])
 def test_device_validation(bad):
     B = synth.poisson_csr(20, 30, 4.0, 1)
@@ -183,25 +205,27 @@ def test_device_validation(bad):
 
 
 @pytest.mark.parametrize("side", ["A", "B"])
-@pytest.mark.parametrize("pos", [0, 63, 64, 130, 199])
+@pytest.mark.parametrize("length,pos", [(200, 0), (200, 63), (200, 64), (200, 130), (200, 199),
+                                        (20, 0), (20, 10), (20, 19)])
 @pytest.mark.parametrize("bad", ["unsorted", "duplicate", "out_of_range"])
-def test_device_validation_long_rows(side, pos, bad):
-    # rows of 200 entries take the wave-cooperative check; the planted error
-    # sits at chunk starts, chunk ends and the row's last entry
-    M = wide_rows(40, 500, 200, 7)
+def test_device_validation_long_rows(side, length, pos, bad):
+    # rows of more than 16 entries take the wave-cooperative check; the planted
+    # error sits at chunk starts, chunk ends and the row's last entry
+    M = wide_rows(40, 500, length, 7)
     rp, ci = M.row_ptr.copy(), M.col_idx.copy()
     s = int(rp[17])
     q = s + pos
+    last = length - 1
     if bad == "unsorted":
-        a, b2 = (q, q + 1) if pos < 199 else (q - 1, q)
+        a, b2 = (q, q + 1) if pos < last else (q - 1, q)
         ci[a], ci[b2] = ci[b2], ci[a]
     elif bad == "duplicate":
-        if pos < 199:
+        if pos < last:
             ci[q + 1] = ci[q]
         else:
             ci[q] = ci[q - 1]
     else:
-        ci[q] = 500 if pos == 199 else -3
+        ci[q] = 500 if pos == last else -3
     Mbad = synth.Csr(M.nrows, M.ncols, rp, ci, M.values)
     if side == "A":
         X, Y = Mbad, synth.poisson_csr(500, 30, 4.0, 1)
