@@ -129,6 +129,22 @@ __device__ __forceinline__ int find_prob(const int32_t *base, int nprob, int g)
     return lo;
 }
 
+// Product lookup with a per-lane memory of the last product found: rows a
+// lane takes in a row usually belong to the same product of a batch, and then
+// two compares replace the binary search.
+struct ProbCache {
+    int t = 0, lo = 0, hi = 0;   // rows [lo, hi) belong to product t
+};
+
+__device__ __forceinline__ int find_prob_cached(const int32_t *base, int nprob, int g, ProbCache &c)
+{
+    if (g >= c.lo && g < c.hi) return c.t;
+    c.t = find_prob(base, nprob, g);
+    c.lo = gp(base)[c.t];
+    c.hi = gp(base)[c.t + 1];
+    return c.t;
+}
+
 // The descriptor of product t by value: from the kernel arguments for a
 // single product, from global memory for a batch.
 __device__ __forceinline__ Prob get_prob(const Batch &b, int t)

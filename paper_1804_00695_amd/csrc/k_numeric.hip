@@ -143,14 +143,14 @@ __device__ __forceinline__ Prob prob_of(const Batch &b, int t)
 }
 
 template <bool MULTI>
-__device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, bool active, int g)
+__device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, bool active, int g, ProbCache &pc)
 {
     RowMeta m{0, 0, 0, 0, 0, active};
     if (!active) return m;
     int i = g;
     if (MULTI) {
-        m.t = find_prob(b.abase, b.nprob, g);
-        i = g - gp(b.abase)[m.t];
+        m.t = find_prob_cached(b.abase, b.nprob, g, pc);
+        i = g - pc.lo;
     }
     const Prob P = prob_of<MULTI>(b, m.t);
     m.nc = gp(sc.val)[g];
@@ -189,7 +189,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
     int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
     int g_cur = -1;
     if (task >= 0 && task * W + slot < n_bin) g_cur = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
-    RowMeta m = row_meta<MULTI>(b, sc, g_cur >= 0, g_cur);
+    ProbCache pc;
+    RowMeta m = row_meta<MULTI>(b, sc, g_cur >= 0, g_cur, pc);
     while (task >= 0) {
         const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
         const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
             tab.insert(logcap, cci[cs + e], e);
             acc[e] = accumulate ? cval[cs + e] : 0.0;
         }
-        m = row_meta<MULTI>(b, sc, act_n, g_n);
+        m = row_meta<MULTI>(b, sc, act_n, g_n, pc);
         nwave_sync();
         bool bad = false;
         for (int pc = ps; pc < pe; pc += G) {

@@ -269,13 +269,14 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
     if (threadIdx.x == 0) tsum = 0;
     __syncthreads();
     const int g0 = blockIdx.x * kBinRowsPerWG;
+    ProbCache pc;
     if (mode == kModeNumeric) {   // size = nnz(C_i): one thread per row
         for (int r = threadIdx.x; r < kBinRowsPerWG; r += kWG) {
             const int g = g0 + r;
             if (g >= b.na) break;
-            const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+            const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
             const Prob P = get_prob(b, t);
-            const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+            const int i = g - (b.nprob == 1 ? 0 : pc.lo);
             const int nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
             const int c = class_of(mode, nc, force_spill);
             gpw(sc.val)[g] = nc;
@@ -290,9 +291,9 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
     for (int r = slot; r < kBinRowsPerWG; r += kBinSlots) {
         const int g = g0 + r;
         if (g >= b.na) break;   // uniform per row group
-        const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+        const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
         const Prob P = get_prob(b, t);
-        const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        const int i = g - (b.nprob == 1 ? 0 : pc.lo);
         // fill pass: rows whose words the count pass kept are expanded, not binned
         const bool from_scratch = mode == kModeFill && sc.scr && gp(sc.scnt)[g] >= 0;
         int64_t size = 0;

@@ -59,14 +59,14 @@ struct SymRow {
     int g, t, i, size, ps, pe;
 };
 
-__device__ __forceinline__ SymRow sym_row(const Batch &b, const Sched &sc, int g)
+__device__ __forceinline__ SymRow sym_row(const Batch &b, const Sched &sc, int g, ProbCache &pc)
 {
     SymRow m{g, 0, 0, 0, 0, 0};
     if (g < 0) return m;
     m.i = g;
     if (b.nprob > 1) {
-        m.t = find_prob(b.abase, b.nprob, g);
-        m.i = g - gp(b.abase)[m.t];
+        m.t = find_prob_cached(b.abase, b.nprob, g, pc);
+        m.i = g - pc.lo;
     }
     const Prob P = get_prob(b, m.t);
     m.size = gp(sc.val)[g];
@@ -110,7 +110,8 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
     int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
     int g_first = -1;
     if (task >= 0 && task * W + slot < n_bin) g_first = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
-    SymRow m = sym_row(b, sc, g_first);
+    ProbCache pc;
+    SymRow m = sym_row(b, sc, g_first, pc);
     while (task >= 0) {
         const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
         const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
                 }
             }
         }
-        m = sym_row(b, sc, g_n);
+        m = sym_row(b, sc, g_n, pc);
         wave_sync();
         if (!FILL) {
             // popcount of the union and number of occupied slots; each lane owns
@@ -361,21 +362,25 @@ static_assert(kScratchWords == kWave, "one scratch word per lane");
 constexpr int kExpandSmall = 16;   // rows with at most this many words take the 16-lane kernel
 
 struct ExpandRow {
-    int cs, ce;
+    int cs, ce, t;
     u32x2 w;
 };
 
-// Scratch words (lane < n) and C row bounds of global row g.
-__device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc, int g, int n, int lane)
+// Scratch words (lane < n), product and C row bounds of global row g.
+__device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc, int g, int n, int lane,
+                                                 ProbCache &pc)
 {
     ExpandRow r;
-    r.cs = 0; r.ce = 0;
+    r.cs = 0; r.ce = 0; r.t = 0;
     r.w.x = 0u; r.w.y = 0u;
     if (g < 0) return r;
     if (lane < n) r.w = ((const MLS_G u32x2 *)sc.scr)[(int64_t)g * kScratchWords + lane];
-    const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
-    const Prob P = get_prob(b, t);
-    const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+    int i = g;
+    if (b.nprob > 1) {
+        r.t = find_prob_cached(b.abase, b.nprob, g, pc);
+        i = g - pc.lo;
+    }
+    const Prob P = get_prob(b, r.t);
     r.cs = gp(P.crp)[i] - P.c_off;
     r.ce = gp(P.crp)[i + 1] - P.c_off;
     return r;
@@ -390,6 +395,7 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
     const int nw = (int)gridDim.x * (kWG / kWave);
     const int w0 = (int)((blockIdx.x * kWG + threadIdx.x) >> 6);
     const MLS_G int32_t *scnt = gp(sc.scnt);
+    ProbCache pc;
     for (int base = w0 * kWave; base < b.na; base += nw * kWave) {
         const int gl = base + lane;
         const int nl = gl < b.na ? scnt[gl] : 0;
@@ -398,7 +404,7 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
         int r = __ffsll((long long)big) - 1;
         big &= big - 1ull;
         int n = __builtin_amdgcn_readlane(nl, r);
-        ExpandRow cur = expand_load(b, sc, base + r, n, lane);
+        ExpandRow cur = expand_load(b, sc, base + r, n, lane, pc);
         for (;;) {
             // prefetch the next large row of this chunk
             int rn = -1, nn = 0;
@@ -407,10 +413,8 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
                 big &= big - 1ull;
                 nn = __builtin_amdgcn_readlane(nl, rn);
             }
-            const ExpandRow nxt = expand_load(b, sc, rn >= 0 ? base + rn : -1, nn, lane);
-            const int g = base + r;
-            const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
-            MLS_G int32_t *__restrict__ cci = gpw(get_prob(b, t).cci);
+            const ExpandRow nxt = expand_load(b, sc, rn >= 0 ? base + rn : -1, nn, lane, pc);
+            MLS_G int32_t *__restrict__ cci = gpw(get_prob(b, cur.t).cci);
             const uint32_t set = cur.w.x;
             // set < 2^26 (columns < 2^31) and a popcount <= 32 share one word:
             // set << 6 | popcount, so one lane read carries both, and
@@ -458,6 +462,7 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
     const int na = b.na;
     // every group of a wave runs the same number of iterations (the shuffles need them all)
     const int nit = (na - (int)(blockIdx.x * (kWG / G)) + rows_per_grid - 1) / rows_per_grid;
+    ProbCache pc;
     for (int it = 0; it < nit; ++it) {
         const int g = first + it * rows_per_grid;
         int n = g < na ? scnt[g] : 0;
@@ -474,9 +479,9 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
             off += kf < base ? (int)(kf & 63u) : 0;
         }
         if (lane < n) {
-            const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+            const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
             const Prob P = get_prob(b, t);
-            const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+            const int i = g - (b.nprob == 1 ? 0 : pc.lo);
             const int cs = gp(P.crp)[i] - P.c_off;
             const int ce = gp(P.crp)[i + 1] - P.c_off;
             MLS_G int32_t *__restrict__ cci = gpw(P.cci);
