@@ -371,11 +371,18 @@ __global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
     if (threadIdx.x < kNumBins) gpw(sc.bin_count)[threadIdx.x] = (int32_t)s_tot[threadIdx.x];
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
+    constexpr int kPer = 8;   // consecutive blocks per thread and step
     for (int c = 0; c < kNumBins; ++c) {
-        for (int x0 = 0; x0 < nblk; x0 += kWG) {
-            const int x = x0 + threadIdx.x;
-            const int64_t v = x < nblk ? blk[c * stride + x] : 0;
-            int64_t incl = v;
+        for (int x0 = 0; x0 < nblk; x0 += kWG * kPer) {
+            const int xb = x0 + threadIdx.x * kPer;
+            int32_t v[kPer];
+            int64_t sum = 0;
+#pragma unroll
+            for (int d = 0; d < kPer; ++d) {
+                v[d] = xb + d < nblk ? blk[c * stride + xb + d] : 0;
+                sum += v[d];
+            }
+            int64_t incl = sum;
 #pragma unroll
             for (int o = 1; o < kWave; o <<= 1) {
                 const int64_t y = __shfl_up(incl, o, kWave);
@@ -383,9 +390,13 @@ __global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
             }
             if (lane == 63) s_red[wave] = incl;
             __syncthreads();
-            int64_t off = s_carry;
+            int64_t off = s_carry + incl - sum;
             for (int w = 0; w < wave; ++w) off += s_red[w];
-            if (x < nblk) blk[c * stride + x] = (int32_t)(off + incl - v);
+#pragma unroll
+            for (int d = 0; d < kPer; ++d) {
+                if (xb + d < nblk) blk[c * stride + xb + d] = (int32_t)off;
+                off += v[d];
+            }
             __syncthreads();
             if (threadIdx.x == 0) {
                 int64_t t = 0;

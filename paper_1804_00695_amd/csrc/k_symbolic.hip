@@ -76,7 +76,7 @@ __device__ __forceinline__ SymRow sym_row(const Batch &b, const Sched &sc, int g
 }
 
 template <int G, int CAP, bool FILL>
-__global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 5))) void k_sym_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
     constexpr int ROWB = FILL ? CAP * 12 : CAP * 8;
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
     if (task >= 0 && task * W + slot < n_bin) g_first = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
     ProbCache pc;
     SymRow m = sym_row(b, sc, g_first, pc);
+    int pre_q0 = 0, pre_nw = -1;   // the current row's first-chunk B row, when located in advance
     while (task >= 0) {
         const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
         const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
@@ -145,11 +146,18 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
             const int b_off = P.b_off, k_lo = P.k_lo, k_hi = P.k_hi;
             const int ps = m.ps, pe = m.pe;
             for (int p = ps + lane; p < pe; p += G) {
-                int k = aci[p];
-                if (k < k_lo || k >= k_hi) continue;
-                int kl = k - k_lo;
-                const MLS_G u32x2 *w = bw + (brp[kl] - b_off);
-                const int nw = bwc[kl];
+                int q0, nw;
+                if (p == ps + lane && pre_nw >= 0) {   // first chunk: B row located during the previous row
+                    q0 = pre_q0;
+                    nw = pre_nw;
+                } else {
+                    const int k = aci[p];
+                    if (k < k_lo || k >= k_hi) continue;
+                    const int kl = k - k_lo;
+                    q0 = brp[kl] - b_off;
+                    nw = bwc[kl];
+                }
+                const MLS_G u32x2 *w = bw + q0;
                 for (int x = 0; x < nw; x += kSymBatch) {
                     u32x2 wd[kSymBatch];
 #pragma unroll
@@ -163,6 +171,11 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
         }
         m = sym_row(b, sc, g_n, pc);
         wave_sync();
+        // locate the next row's first chunk of B rows while this row is finished:
+        // the entry of A, then the B row's word offset and count
+        pre_nw = -1;
+        int pre_k = -1;
+        if (m.g >= 0 && m.ps + lane < m.pe) pre_k = gp(get_prob(b, m.t).aci)[m.ps + lane];
         if (!FILL) {
             // popcount of the union and number of occupied slots; each lane owns
             // 4 (vec) or 1 consecutive slots per pass
@@ -181,6 +194,13 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
             }
             c = group_sum<G>(c);
             nsets = group_sum<G>(nsets);
+            if (pre_k >= 0) {
+                const Prob Pn = get_prob(b, m.t);
+                if (pre_k >= Pn.k_lo && pre_k < Pn.k_hi) {
+                    pre_q0 = gp(Pn.brp)[pre_k - Pn.k_lo] - Pn.b_off;
+                    pre_nw = gp(Pn.bwc)[pre_k - Pn.k_lo];
+                }
+            }
             if (active && lane == 0) val[g] = c;
             if (sc.scr) {
                 // keep the row's words for the fill pass (compacted in slot order)
@@ -225,6 +245,13 @@ __global__ __launch_bounds__(kWG) void k_sym_lds(Batch b, Sched sc, int bin)
                 }
             }
         } else {
+            if (pre_k >= 0) {
+                const Prob Pn = get_prob(b, m.t);
+                if (pre_k >= Pn.k_lo && pre_k < Pn.k_hi) {
+                    pre_q0 = gp(Pn.brp)[pre_k - Pn.k_lo] - Pn.b_off;
+                    pre_nw = gp(Pn.bwc)[pre_k - Pn.k_lo];
+                }
+            }
             for (int h = lane; h < cap; h += G) {
                 uint32_t k = key[h];
                 if (k != kEmptyKey) {
@@ -449,50 +476,65 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
     }
 }
 
-// Rows of at most kExpandSmall words: 16 lanes per row, four rows per wave;
-// word f of the row is read from lane f of the group by a lane shuffle.
+// Rows of at most kExpandSmall words: a wave reads the word counts of 64
+// consecutive rows and takes the small non-empty ones four at a time, 16
+// lanes per row; word f of a row is read from lane f of its group by a lane
+// shuffle.
 __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
 {
     constexpr int G = kExpandSmall;
-    const int lane = threadIdx.x % G;
-    const int rows_per_grid = (int)gridDim.x * (kWG / G);
+    const int lane64 = threadIdx.x & 63;
+    const int slot = lane64 / G, lane = lane64 % G;
+    const int nw = (int)gridDim.x * (kWG / kWave);
+    const int w0 = (int)((blockIdx.x * kWG + threadIdx.x) >> 6);
     const MLS_G int32_t *scnt = gp(sc.scnt);
     const MLS_G u32x2 *scr = (const MLS_G u32x2 *)sc.scr;
-    const int first = (int)(blockIdx.x * (kWG / G) + threadIdx.x / G);
-    const int na = b.na;
-    // every group of a wave runs the same number of iterations (the shuffles need them all)
-    const int nit = (na - (int)(blockIdx.x * (kWG / G)) + rows_per_grid - 1) / rows_per_grid;
     ProbCache pc;
-    for (int it = 0; it < nit; ++it) {
-        const int g = first + it * rows_per_grid;
-        int n = g < na ? scnt[g] : 0;
-        if (n > G) n = 0;   // larger rows belong to the wave-per-row kernel
-        u32x2 w;
-        w.x = 0u; w.y = 0u;
-        if (lane < n) w = scr[(int64_t)g * kScratchWords + lane];
-        const uint32_t base = w.x << 6;
-        const uint32_t key = base | (uint32_t)(lane < n ? __popc(w.y) : 0);
-        int off = 0;
+    for (int base = w0 * kWave; base < b.na; base += nw * kWave) {
+        const int gl = base + lane64;
+        const int nl = gl < b.na ? scnt[gl] : 0;
+        unsigned long long small = __ballot(nl > 0 && nl <= G);
+        while (small) {
+            // the next four small rows of the chunk, one per group of 16 lanes
+            int pick = -1;
 #pragma unroll
-        for (int f = 0; f < G; ++f) {
-            const uint32_t kf = (uint32_t)__shfl((int)key, f, G);
-            off += kf < base ? (int)(kf & 63u) : 0;
-        }
-        if (lane < n) {
-            const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
-            const Prob P = get_prob(b, t);
-            const int i = g - (b.nprob == 1 ? 0 : pc.lo);
-            const int cs = gp(P.crp)[i] - P.c_off;
-            const int ce = gp(P.crp)[i + 1] - P.c_off;
-            MLS_G int32_t *__restrict__ cci = gpw(P.cci);
-            uint32_t m = w.y;
-            int pos = cs + off;
-            while (m) {
-                const int bit = __ffs(m) - 1;
-                if (pos < ce) cci[pos] = (int32_t)(w.x * 32u + (uint32_t)bit);
-                else atomicOr(sc.err, kErrStructure);
-                ++pos;
-                m &= m - 1u;
+            for (int j = 0; j < kWave / G; ++j) {
+                const int r = small ? __ffsll((long long)small) - 1 : -1;
+                if (small) small &= small - 1ull;
+                if (j == slot) pick = r;
+            }
+            // every lane takes part in the shuffle: a source lane of a group without a row
+            // must still provide its value
+            int n = __shfl(nl, pick >= 0 ? pick : 0, kWave);
+            if (pick < 0) n = 0;
+            const int g = base + pick;
+            u32x2 w;
+            w.x = 0u; w.y = 0u;
+            if (lane < n) w = scr[(int64_t)g * kScratchWords + lane];
+            const uint32_t kb = w.x << 6;
+            const uint32_t key = kb | (uint32_t)(lane < n ? __popc(w.y) : 0);
+            int off = 0;
+#pragma unroll
+            for (int f = 0; f < G; ++f) {
+                const uint32_t kf = (uint32_t)__shfl((int)key, f, G);
+                off += kf < kb ? (int)(kf & 63u) : 0;
+            }
+            if (lane < n) {
+                const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
+                const Prob P = get_prob(b, t);
+                const int i = g - (b.nprob == 1 ? 0 : pc.lo);
+                const int cs = gp(P.crp)[i] - P.c_off;
+                const int ce = gp(P.crp)[i + 1] - P.c_off;
+                MLS_G int32_t *__restrict__ cci = gpw(P.cci);
+                uint32_t m = w.y;
+                int pos = cs + off;
+                while (m) {
+                    const int bit = __ffs(m) - 1;
+                    if (pos < ce) cci[pos] = (int32_t)(w.x * 32u + (uint32_t)bit);
+                    else atomicOr(sc.err, kErrStructure);
+                    ++pos;
+                    m &= m - 1u;
+                }
             }
         }
     }
