@@ -4,9 +4,9 @@
 // LDS path: G lanes own one row; the lanes walk the entries of row i of A
 // (one k per lane) and OR every (set, mask) word of compressed B_k into an
 // open-addressing hash table in LDS keyed by set. Count pass: rownnz =
-// sum of popcounts. Fill pass: the occupied (set, mask) pairs are compacted;
-// each pair's output offset is the popcount sum of the pairs with a smaller
-// set (so no sort is needed), and its bits expand into ascending columns.
+// sum of popcounts. Fill pass: the occupied (set, mask) pairs are compacted,
+// sorted by set in LDS (bitonic network), and their bits expand into
+// ascending columns at offsets from a scan of the popcounts.
 //
 // Spill path (rows whose word bound exceeds the largest LDS class): one
 // workgroup per row with a dense bitmap over all columns in global memory;
@@ -261,22 +261,47 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 
                 }
             }
             wave_sync();
+            // sort the row's (set, mask) words by set (bitonic network over the
+            // list padded to a power of two with sets that sort last), then
+            // give each lane a contiguous run of words: an exclusive scan of
+            // the runs' popcounts places every word's bits in the output row
+            const int n = active ? min(s_cnt[rs], LIST) : 0;
+            int npad = 1;
+            while (npad < n) npad <<= 1;
+            for (int e = n + lane; e < npad; e += G) list[e] = make_uint2(kEmptyKey, 0u);
+            wave_sync();
+            for (int kk = 2; kk <= npad; kk <<= 1) {
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    for (int e = lane; e < npad; e += G) {
+                        const int l = e ^ j;
+                        if (l > e) {
+                            const uint2 ae = list[e], al = list[l];
+                            if ((ae.x > al.x) == ((e & kk) == 0)) { list[e] = al; list[l] = ae; }
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+            const int per = (n + G - 1) / G;
+            const int e0 = min(lane * per, n), e1 = min(e0 + per, n);
+            int run = 0;
+            for (int e = e0; e < e1; ++e) run += __popc(list[e].y);
+            int incl = run;
+#pragma unroll
+            for (int o = 1; o < G; o <<= 1) {
+                const int y = __shfl_up(incl, o, G);
+                if (lane >= o) incl += y;
+            }
             if (active) {
-                const int n = min(s_cnt[rs], LIST);
                 const int cs = gp(P.crp)[i] - P.c_off;
                 const int ce = gp(P.crp)[i + 1] - P.c_off;
                 MLS_G int32_t *__restrict__ cci = gpw(P.cci);
-                for (int e = lane; e < n; e += G) {
-                    uint2 me = list[e];
-                    int off = 0;
-                    for (int f = 0; f < n; ++f) {
-                        uint2 o = list[f];
-                        off += (o.x < me.x) ? __popc(o.y) : 0;
-                    }
+                int pos = cs + incl - run;
+                for (int e = e0; e < e1; ++e) {
+                    const uint2 me = list[e];
                     uint32_t m = me.y;
-                    int pos = cs + off;
                     while (m) {
-                        int bit = __ffs(m) - 1;
+                        const int bit = __ffs(m) - 1;
                         if (pos < ce) cci[pos] = (int32_t)(me.x * 32u + (uint32_t)bit);
                         else atomicOr(sc.err, kErrStructure);
                         ++pos;
