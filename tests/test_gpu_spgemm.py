@@ -108,6 +108,26 @@ def test_forced_spill_identical():
     check(synth.poisson_csr(300, 300, 5.0, 9), synth.poisson_csr(300, 400, 5.0, 10))
 
 
+def test_class_boundaries():
+    # rows of C with exactly the sizes where the LDS classes change (32/33,
+    # 128/129, 512/513, 2048/2049 outputs; the count bound equals the row
+    # length here, so 128/129, 512/513, 2048/2049 and 8192/8193 for the count
+    # classes)
+    lengths = [1, 31, 32, 33, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1024, 2047, 2048, 2049,
+               4096, 8192, 8193, 9000]
+    n = 20000
+    g = synth.rng(17)
+    rows = [np.sort(g.choice(n, L, replace=False)) for L in lengths]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    A = synth.Csr(len(rows), n, rp, np.concatenate(rows).astype(np.int32), g.standard_normal(int(rp[-1])))
+    # B: row k holds the single column 32 * (k % 625) + k // 625 (a permutation), so every B row is one
+    # word and C's row i has exactly as many columns as A's row i
+    cols = (32 * (np.arange(n) % 625) + np.arange(n) // 625).astype(np.int32)
+    B = synth.Csr(n, n, np.arange(n + 1, dtype=np.int32), cols, g.standard_normal(n))
+    R = check(A, B)
+    assert np.array_equal(np.diff(R.row_ptr), lengths)
+
+
 def test_wide_table_identical():
     # the 8-byte (column, position) slots, which products with many columns use
     mls.set_option(mls._abi.OPT_WIDE_TABLE, 1)
