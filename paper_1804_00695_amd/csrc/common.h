@@ -16,10 +16,10 @@ namespace mls {
 constexpr int kWG = 256;          // threads per workgroup
 constexpr int kWave = 64;         // gfx950 wavefront
 constexpr int kXcd = 8;           // MI355X: 8 accelerator complex dies, 32 CUs each
-constexpr int kNumClasses = 4;    // LDS classes
-constexpr int kNumBins = 6;       // 4 LDS classes, spill, empty
-constexpr int kBinSpill = 4;
-constexpr int kBinEmpty = 5;
+constexpr int kNumClasses = 5;    // LDS classes
+constexpr int kNumBins = 7;       // 5 LDS classes, spill, empty
+constexpr int kBinSpill = 5;
+constexpr int kBinEmpty = 6;
 
 // Error bits (device flag).
 constexpr uint32_t kErrBadCsr = 1u;
@@ -27,13 +27,13 @@ constexpr uint32_t kErrOverflow = 2u;
 constexpr uint32_t kErrStructure = 4u;
 constexpr uint32_t kErrTable = 8u;
 
-// LDS capacities (hash slots) of the four classes, per phase. A row goes to
+// LDS capacities (hash slots) of the five classes, per phase. A row goes to
 // the first class whose threshold holds; beyond class 3 it spills. The
 // smallest class keeps many short rows in flight (small tables, 8 lanes).
 //   count  : threshold on the word upper bound u, table = u slots at most
 //   fill / numeric / tc : threshold on the exact size n, table >= 2n slots
-constexpr int kCountCap[kNumClasses] = {128, 512, 2048, 8192};
-constexpr int kFillCap[kNumClasses] = {64, 256, 1024, 4096};
+constexpr int kCountCap[kNumClasses] = {128, 256, 512, 2048, 8192};
+constexpr int kFillCap[kNumClasses] = {64, 256, 1024, 2048, 4096};
 
 struct Prob {
     // A (or an A/C row part): row pointers hold global entry offsets; the

@@ -25,7 +25,7 @@ extern thread_local int g_last_hip_error;
 constexpr size_t kHdrBytes = 1024;
 constexpr size_t kHdrErr = 0;
 constexpr size_t kHdrBinCount = 64;
-constexpr size_t kHdrTaskCursor = 192;   // kNumBins * kXcd int32
+constexpr size_t kHdrTaskCursor = 192;   // kNumBins * kXcd int32 (up to 224 bytes)
 constexpr size_t kHdrTotal = 512;        // uint64
 
 struct Layout {

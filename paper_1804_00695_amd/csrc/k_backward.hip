@@ -233,6 +233,7 @@ void launch_backward(const Batch &b, const Sched &sc, const double *wval, double
     if (G >= 64) launch_bwd_class<64, kFillCap[2]>(b, sc, 2, dA, dB, s);
     else launch_bwd_class<32, kFillCap[2]>(b, sc, 2, dA, dB, s);
     launch_bwd_class<64, kFillCap[3]>(b, sc, 3, dA, dB, s);
+    launch_bwd_class<64, kFillCap[4]>(b, sc, 4, dA, dB, s);
     static int spill_grid = device_cu_count();
     ProfScope ps("bwd_spill", s);
     hipLaunchKernelGGL(k_bwd_spill, dim3(spill_grid), dim3(kWG), 0, s, b, sc, dA, dB);

@@ -52,8 +52,8 @@ constexpr int nw_num(int row_bytes, int rows_per_wave)
 // column range excludes the all-ones column field.
 template <int CAP>
 struct PackBits {
-    static constexpr int PB = CAP == 64 ? 5 : (CAP == 256 ? 7 : (CAP == 1024 ? 9 : 11));
-    static_assert(CAP == 64 || CAP == 256 || CAP == 1024 || CAP == 4096, "table class");
+    static constexpr int PB = CAP == 64 ? 5 : (CAP == 256 ? 7 : (CAP == 1024 ? 9 : (CAP == 2048 ? 10 : 11)));
+    static_assert(CAP == 64 || CAP == 256 || CAP == 1024 || CAP == 2048 || CAP == 4096, "table class");
     static constexpr uint32_t kMaxCols = (1u << (32 - PB)) - 1u;   // columns < this fit
 };
 
@@ -401,6 +401,7 @@ void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s)
     if (G >= 64) launch_num_class<64, kFillCap[2]>(b, sc, 2, s);
     else launch_num_class<32, kFillCap[2]>(b, sc, 2, s);
     launch_num_class<64, kFillCap[3]>(b, sc, 3, s);
+    launch_num_class<64, kFillCap[4]>(b, sc, 4, s);
     static int spill_grid = device_cu_count();
     ProfScope ps("num_spill", s);
     hipLaunchKernelGGL(k_num_spill, dim3(spill_grid), dim3(kWG), 0, s, b, sc);

@@ -20,7 +20,7 @@
 namespace mls {
 
 constexpr uint32_t kEmptyKey = 0xffffffffu;
-constexpr int kSymBatch = 12;  // words of one B_k row loaded before they are inserted
+constexpr int kSymBatch = 6;   // words of one B_k row loaded before they are inserted (measured)
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -76,7 +76,7 @@ __device__ __forceinline__ SymRow sym_row(const Batch &b, const Sched &sc, int g
 }
 
 template <int G, int CAP, bool FILL>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 5))) void k_sym_lds(Batch b, Sched sc, int bin)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 6))) void k_sym_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
     constexpr int ROWB = FILL ? CAP * 12 : CAP * 8;
@@ -608,6 +608,7 @@ static void launch_sym_all(const Batch &b, const Sched &sc, int G, hipStream_t s
     constexpr int C1 = FILL ? kFillCap[1] : kCountCap[1];
     constexpr int C2 = FILL ? kFillCap[2] : kCountCap[2];
     constexpr int C3 = FILL ? kFillCap[3] : kCountCap[3];
+    constexpr int C4 = FILL ? kFillCap[4] : kCountCap[4];
     launch_sym_class<8, C0, FILL>(b, sc, 0, s);
     switch (G) {
     case 8: launch_sym_class<8, C1, FILL>(b, sc, 1, s); break;
@@ -615,9 +616,20 @@ static void launch_sym_all(const Batch &b, const Sched &sc, int G, hipStream_t s
     case 64: launch_sym_class<64, C1, FILL>(b, sc, 1, s); break;
     default: launch_sym_class<32, C1, FILL>(b, sc, 1, s); break;
     }
-    if (G >= 64) launch_sym_class<64, C2, FILL>(b, sc, 2, s);
-    else launch_sym_class<32, C2, FILL>(b, sc, 2, s);
-    launch_sym_class<64, C3, FILL>(b, sc, 3, s);
+    if (FILL) {   // fill tables are twice the row size: class 2 is already large
+        if (G >= 64) launch_sym_class<64, C2, FILL>(b, sc, 2, s);
+        else launch_sym_class<32, C2, FILL>(b, sc, 2, s);
+    } else {
+        switch (G) {
+        case 8: launch_sym_class<8, C2, FILL>(b, sc, 2, s); break;
+        case 16: launch_sym_class<16, C2, FILL>(b, sc, 2, s); break;
+        case 64: launch_sym_class<64, C2, FILL>(b, sc, 2, s); break;
+        default: launch_sym_class<32, C2, FILL>(b, sc, 2, s); break;
+        }
+    }
+    if (G >= 64) launch_sym_class<64, C3, FILL>(b, sc, 3, s);
+    else launch_sym_class<32, C3, FILL>(b, sc, 3, s);
+    launch_sym_class<64, C4, FILL>(b, sc, 4, s);
 }
 
 void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, uint32_t *spill_bitmaps, int spill_slots,

@@ -307,6 +307,7 @@ void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long l
     launch_tc_class<32, kFillCap[1], 8, 1>(b, sc, 1, counts, s);
     launch_tc_class<64, kFillCap[2], 8, 1>(b, sc, 2, counts, s);
     launch_tc_class<64, kFillCap[3], 8, 1>(b, sc, 3, counts, s);
+    launch_tc_class<64, kFillCap[4], 8, 1>(b, sc, 4, counts, s);
     {
         ProfScope ps("tc_spill", s);
         hipLaunchKernelGGL(k_tc_spill, dim3(spill_slots), dim3(kWG), 0, s, b, sc, counts, spill_bitmaps, spill_words);

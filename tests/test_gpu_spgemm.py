@@ -110,10 +110,10 @@ def test_forced_spill_identical():
 
 def test_class_boundaries():
     # rows of C with exactly the sizes where the LDS classes change (32/33,
-    # 128/129, 512/513, 2048/2049 outputs; the count bound equals the row
-    # length here, so 128/129, 512/513, 2048/2049 and 8192/8193 for the count
-    # classes)
-    lengths = [1, 31, 32, 33, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1024, 2047, 2048, 2049,
+    # 128/129, 512/513, 1024/1025, 2048/2049 outputs; the count bound equals
+    # the row length here, so 128/129, 256/257, 512/513, 2048/2049 and
+    # 8192/8193 for the count classes)
+    lengths = [1, 31, 32, 33, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1024, 1025, 2047, 2048, 2049,
                4096, 8192, 8193, 9000]
     n = 20000
     g = synth.rng(17)
