@@ -83,8 +83,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 
     constexpr int NW = nw_for(ROWB, W);
     constexpr int LIST = FILL ? CAP / 2 : 1;
     // the fill pass's (set, mask) lists and counters follow the keys; the
-    // count pass allocates nothing beyond the two tables, so that four
-    // 32 KB workgroups of the largest-volume class fit one CU with room for a fifth
+    // count pass allocates nothing beyond the two tables, so that its
+    // workgroups use exactly 16 or 32 KB and tile the 160 KB of LDS of a CU
     constexpr int EXTRA = FILL ? NW * W * (2 * LIST + 1) : 0;
     __shared__ __attribute__((aligned(16))) uint32_t s_key[NW * W * CAP + EXTRA];
     __shared__ __attribute__((aligned(16))) uint32_t s_msk[NW * W * CAP];
