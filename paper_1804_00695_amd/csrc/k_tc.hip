@@ -34,11 +34,49 @@ constexpr int nw_tc(int row_bytes, int rows_per_wave)
     return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
 }
 
+// A row of L as the pipeline holds it: index (-1 for none), own word count,
+// entry range, the lane's first own word, and the lane's first staged entry
+// k with the offset and word count of row k of comp(L).
+struct TcRow {
+    int i, size, ps, pe, k, st, nk;
+    u32x2 w;
+};
+
+__device__ __forceinline__ TcRow tc_row(const MLS_G int32_t *lrp, const MLS_G int32_t *val, int g)
+{
+    TcRow r;
+    r.i = g; r.size = 0; r.ps = 0; r.pe = 0; r.k = -1; r.st = 0; r.nk = 0;
+    r.w.x = 0u; r.w.y = 0u;
+    if (g >= 0) {
+        r.size = val[g];
+        r.ps = lrp[g];
+        r.pe = lrp[g + 1];
+    }
+    return r;
+}
+
+__device__ __forceinline__ void tc_row_words(TcRow &r, const MLS_G int32_t *lrp, const MLS_G int32_t *lci,
+                                             const MLS_G u32x2 *bw, int lane)
+{
+    (void)lrp;
+    if (r.i < 0) return;
+    if (lane < r.size) r.w = bw[r.ps + lane];
+    if (r.ps + lane < r.pe) r.k = lci[r.ps + lane];
+}
+
+__device__ __forceinline__ void tc_row_entry(TcRow &r, const MLS_G int32_t *lrp, const MLS_G int32_t *bwc)
+{
+    if (r.i >= 0 && r.k >= 0) {
+        r.st = lrp[r.k];
+        r.nk = bwc[r.k];
+    }
+}
+
 // LDS per row: the own-word table (key, mask) and the staged entries
 constexpr int tc_row_bytes(int CAP, int G) { return CAP * 8 + G * 12 + 4; }
 
 template <int G, int CAP, int PW, int PP>
-__global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int64_t *counts)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k_tc_lds(Batch b, Sched sc, int bin, int64_t *counts)
 {
     constexpr int W = kWave / G;
     constexpr int NW = nw_tc(tc_row_bytes(CAP, G), W);
@@ -69,27 +107,33 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
     TaskIter it = task_iter(ntasks, NW);
-    for (;;) {
-        int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        if (task < 0) break;
-        const int r = task * W + slot;
-        const int gi = r < n_bin ? bin_row(sc.perm, sc.err, b.na, start + r) : -1;
-        const bool active = gi >= 0;
-        const int i = active ? gi : 0;
-        const int size = active ? val[i] : 0;
+    // Rows are software-pipelined: while a row is counted, the next row's
+    // index, sizes, first own word per lane and first staged entry per lane
+    // (its row of comp(L): offset and word count) are loaded, so a row starts
+    // with only its pieces' words to fetch.
+    int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+    int gi = (task >= 0 && task * W + slot < n_bin) ? bin_row(sc.perm, sc.err, b.na, start + task * W + slot) : -1;
+    TcRow cur = tc_row(lrp, val, gi);
+    tc_row_words(cur, lrp, lci, bw, lane);
+    tc_row_entry(cur, lrp, bwc);
+    while (task >= 0) {
+        const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+        const int gn = (task_n >= 0 && task_n * W + slot < n_bin)
+                           ? bin_row(sc.perm, sc.err, b.na, start + task_n * W + slot) : -1;
+        const bool active = cur.i >= 0;
+        const int i = active ? cur.i : 0;
+        const int size = cur.size;
         int logcap = ilog2_ceil(2 * size);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
         const uint32_t cmask = (uint32_t)cap - 1u;
         for (int h = lane; h < cap; h += G) key[h] = kTcEmpty;
         tc_sync();
-        int ps = 0, pe = 0;
+        const int ps = cur.ps, pe = cur.pe;
         if (active) {
-            ps = lrp[i];
-            pe = lrp[i + 1];
             const MLS_G u32x2 *wi = bw + ps;
             for (int x = lane; x < size; x += G) {
-                u32x2 wd = wi[x];
+                const u32x2 wd = x == lane ? cur.w : wi[x];
                 uint32_t h = hslot(wd.x, logcap);
                 for (uint32_t probe = 0; probe <= cmask; ++probe) {
                     if (atomicCAS(key + h, kTcEmpty, wd.x) == kTcEmpty) { msk[h] = wd.y; break; }
@@ -97,6 +141,7 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
                 }
             }
         }
+        TcRow nxt = tc_row(lrp, val, gn);
         tc_sync();
         uint32_t cnt = 0;
         // Entries k of row i are staged G at a time; the words of row k of
@@ -105,9 +150,16 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
         // does not hold up the group. A piece's entry is found by binary
         // search over the staged first-piece offsets. Pieces hold PW words; PP
         // pieces per lane are in flight at once.
+        bool first = true;
         for (int pc = ps; pc < pe; pc += G) {   // ps == pe for inactive rows
             int st = 0, nk = 0;
-            if (pc + lane < pe) {
+            if (first) {
+                st = cur.st;
+                nk = cur.nk;
+                first = false;
+                // the next row's own word and entry are in flight during this chunk
+                tc_row_words(nxt, lrp, lci, bw, lane);
+            } else if (pc + lane < pe) {
                 const int k = lci[pc + lane];
                 st = lrp[k];
                 nk = bwc[k];
@@ -165,9 +217,13 @@ __global__ __launch_bounds__(kWG) void k_tc_lds(Batch b, Sched sc, int bin, int6
             }
             tc_sync();
         }
+        if (first) tc_row_words(nxt, lrp, lci, bw, lane);
+        tc_row_entry(nxt, lrp, bwc);
         int64_t c = group_sum<G>((int64_t)cnt);
         if (active && lane == 0) gpw(counts)[i] = c;
         tc_sync();
+        cur = nxt;
+        task = task_n;
     }
 }
 
@@ -303,8 +359,8 @@ void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long l
 {
     if (b.na <= 0) return;
     // lanes per row, words per piece, pieces in flight per lane: measured on R-MAT
-    launch_tc_class<16, kFillCap[0], 8, 1>(b, sc, 0, counts, s);
-    launch_tc_class<32, kFillCap[1], 8, 1>(b, sc, 1, counts, s);
+    launch_tc_class<32, kFillCap[0], 8, 1>(b, sc, 0, counts, s);
+    launch_tc_class<64, kFillCap[1], 8, 1>(b, sc, 1, counts, s);
     launch_tc_class<64, kFillCap[2], 8, 1>(b, sc, 2, counts, s);
     launch_tc_class<64, kFillCap[3], 8, 1>(b, sc, 3, counts, s);
     launch_tc_class<64, kFillCap[4], 8, 1>(b, sc, 4, counts, s);
