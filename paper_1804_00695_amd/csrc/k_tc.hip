@@ -19,6 +19,10 @@
 namespace mls {
 
 constexpr uint32_t kTcEmpty = 0xffffffffu;
+// own-word table sizes of the classes (a row's table has at least twice its
+// own words); finer than the symbolic classes between 256 and 1024 slots,
+// where most of the work of power-law graphs sits
+constexpr int kTcCap[kNumClasses] = {64, 256, 512, 1024, 4096};
 
 __device__ __forceinline__ void tc_sync()
 {
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(kWG) void k_tc_bin(Batch b, Sched sc, int force_spi
         else {
             c = kBinSpill;
             for (int x = kNumClasses - 1; x >= 0; --x)
-                if (size <= kFillCap[x] / 2) c = x;
+                if (size <= kTcCap[x] / 2) c = x;
         }
         gpw(sc.val)[i] = size;
         gpw(sc.cls)[i] = (uint8_t)c;
@@ -359,11 +363,11 @@ void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long l
 {
     if (b.na <= 0) return;
     // lanes per row, words per piece, pieces in flight per lane: measured on R-MAT
-    launch_tc_class<32, kFillCap[0], 8, 1>(b, sc, 0, counts, s);
-    launch_tc_class<64, kFillCap[1], 8, 1>(b, sc, 1, counts, s);
-    launch_tc_class<64, kFillCap[2], 8, 1>(b, sc, 2, counts, s);
-    launch_tc_class<64, kFillCap[3], 8, 1>(b, sc, 3, counts, s);
-    launch_tc_class<64, kFillCap[4], 8, 1>(b, sc, 4, counts, s);
+    launch_tc_class<32, kTcCap[0], 8, 1>(b, sc, 0, counts, s);
+    launch_tc_class<64, kTcCap[1], 8, 1>(b, sc, 1, counts, s);
+    launch_tc_class<64, kTcCap[2], 8, 1>(b, sc, 2, counts, s);
+    launch_tc_class<64, kTcCap[3], 8, 1>(b, sc, 3, counts, s);
+    launch_tc_class<64, kTcCap[4], 8, 1>(b, sc, 4, counts, s);
     {
         ProfScope ps("tc_spill", s);
         hipLaunchKernelGGL(k_tc_spill, dim3(spill_slots), dim3(kWG), 0, s, b, sc, counts, spill_bitmaps, spill_words);

@@ -71,3 +71,49 @@ def test_long_spread_rows_and_spill():
     check(G)
     mls.set_option(mls._abi.OPT_FORCE_SPILL, 1)
     check(synth.rmat_graph(11, 8, seed=2))
+
+
+def lower_with_word_rows(targets, n, seed):
+    """Strictly lower L: sparse random rows near the diagonal, plus one row per
+    target w holding exactly w distinct 32-column words (1-3 columns each);
+    rows named by a target's columns share some of them, so they close
+    triangles."""
+    g = synth.rng(seed)
+    rows = [set() for _ in range(n)]
+    for i in range(1, n):
+        k = int(g.integers(0, 5))
+        if k:
+            rows[i].update(g.integers(max(0, i - 2000), i, k).tolist())
+    special = {}
+    for t, w in enumerate(targets):
+        i = n - 1 - 7 * t
+        words = g.choice(i >> 5, size=w, replace=False)
+        cols = set()
+        for q in words.tolist():
+            cols.update((32 * q + g.choice(32, size=int(g.integers(1, 4)), replace=False)).tolist())
+        rows[i] = cols
+        special[i] = w
+        sc = sorted(cols)
+        for j in g.choice(sc, size=min(40, len(sc)), replace=False).tolist():
+            below = [c for c in sc if c < j]
+            if below:
+                rows[j].update(g.choice(below, size=min(20, len(below)), replace=False).tolist())
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate([np.array(sorted(r), dtype=np.int32) for r in rows])
+    for i, w in special.items():
+        assert np.unique(ci[rp[i]:rp[i + 1]] >> 5).size == w
+    return synth.Csr(n, n, rp, ci, None)
+
+
+def test_class_boundaries():
+    # own-word counts on both sides of every class limit (half the table of
+    # 64, 256, 512, 1024 and 4096 slots); the row of 2049 words spills
+    targets = [32, 33, 128, 129, 256, 257, 512, 513, 2048, 2049]
+    L = lower_with_word_rows(targets, 70000, 23)
+    counts, total = mls.triangle_count(mls.DeviceCsr.from_host(L))
+    torch.cuda.synchronize()
+    ref_counts, ref_total = oracle.tc_count(L)
+    assert total == ref_total
+    assert np.array_equal(counts.cpu().numpy(), ref_counts)
+    assert ref_total > 0
