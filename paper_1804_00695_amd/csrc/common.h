@@ -209,22 +209,46 @@ __device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
 // and workgroups that become resident late, or never, leave no tasks behind.
 constexpr int kTaskBlock = 8;
 
+//
+// With log_chunk >= 0 the tasks are instead cut into chunks of 2^log_chunk
+// consecutive tasks, dealt to the XCDs round-robin: each XCD then holds a
+// uniform sample of the bin, for bins whose work per task drifts with the
+// row index (the degree-ordered rows of a power-law graph), where contiguous
+// slabs leave some XCDs idle while others still work.
 struct TaskIter {
-    int lo, hi, S, cur, left;
+    int lo, hi, S, cur, left, x, lc;
 };
 
-__device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg)
+__device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg, int log_chunk = -1)
 {
     const int x = (int)(blockIdx.x % kXcd);
     TaskIter it;
-    it.lo = (int)(((int64_t)ntasks * x) / kXcd);
-    it.hi = (int)(((int64_t)ntasks * (x + 1)) / kXcd);
+    it.x = x;
+    it.lc = log_chunk;
+    if (log_chunk < 0) {
+        it.lo = (int)(((int64_t)ntasks * x) / kXcd);
+        it.hi = (int)(((int64_t)ntasks * (x + 1)) / kXcd);
+    } else {
+        // local tasks of XCD x: the full chunks x, x + 8, ... and the
+        // partial last chunk when it falls on x
+        const int nch = ntasks >> log_chunk;
+        const int rem = ntasks & ((1 << log_chunk) - 1);
+        const int full = nch > x ? (nch - x + kXcd - 1) / kXcd : 0;
+        it.lo = 0;
+        it.hi = (full << log_chunk) + (nch % kXcd == x ? rem : 0);
+    }
     const int wgs_x = ((int)gridDim.x - x + kXcd - 1) / kXcd;   // workgroups on this XCD
     it.S = wgs_x * waves_per_wg;
     if (it.S < 1) it.S = 1;
     it.cur = 0;
     it.left = 0;
     return it;
+}
+
+__device__ __forceinline__ int task_global(const TaskIter &it, int t)
+{
+    if (it.lc < 0) return t;
+    return ((((t >> it.lc) * kXcd) + it.x) << it.lc) + (t & ((1 << it.lc) - 1));
 }
 
 // Next task of this wave, or -1. Uniform across the wave; call with all lanes
@@ -238,7 +262,7 @@ __device__ __forceinline__ int next_task_wave(int32_t *cursor, int ntasks, TaskI
             const int t = it.cur;
             it.cur += it.S;
             --it.left;
-            if (t < it.hi) return t;
+            if (t < it.hi) return task_global(it, t);
             it.left = 0;
         }
         int blk = 0;

@@ -79,8 +79,8 @@ __device__ __forceinline__ void tc_row_entry(TcRow &r, const MLS_G int32_t *lrp,
 // LDS per row: the own-word table (key, mask) and the staged entries
 constexpr int tc_row_bytes(int CAP, int G) { return CAP * 8 + G * 12 + 4; }
 
-template <int G, int CAP, int PW, int PP>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k_tc_lds(Batch b, Sched sc, int bin, int64_t *counts)
+template <int G, int CAP, int PW, int PP, int WPE>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE))) void k_tc_lds(Batch b, Sched sc, int bin, int64_t *counts)
 {
     constexpr int W = kWave / G;
     constexpr int NW = nw_tc(tc_row_bytes(CAP, G), W);
@@ -110,7 +110,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(8))) void k
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
-    TaskIter it = task_iter(ntasks, NW);
+    // the work of a row of L drifts with its degree rank: chunks of 32 tasks
+    // dealt to the XCDs round-robin keep the XCDs evenly loaded
+    TaskIter it = task_iter(ntasks, NW, 5);
     // Rows are software-pipelined: while a row is counted, the next row's
     // index, sizes, first own word per lane and first staged entry per lane
     // (its row of comp(L): offset and word count) are loaded, so a row starts
@@ -335,16 +337,16 @@ static int tc_grid(K kernel, int threads)
     return cus * per_cu;
 }
 
-template <int G, int CAP, int P, int PP>
+template <int G, int CAP, int P, int PP, int WPE = 8>
 static void launch_tc_class(const Batch &b, const Sched &sc, int bin, int64_t *counts, hipStream_t s)
 {
     constexpr int W = kWave / G;
     constexpr int NW = nw_tc(tc_row_bytes(CAP, G), W);
-    static int grid = tc_grid(k_tc_lds<G, CAP, P, PP>, NW * kWave);
+    static int grid = tc_grid(k_tc_lds<G, CAP, P, PP, WPE>, NW * kWave);
     static char name[64];
     if (!name[0]) snprintf(name, sizeof(name), "tc_lds_G%d_C%d", G, CAP);
     ProfScope ps(name, s);
-    hipLaunchKernelGGL((k_tc_lds<G, CAP, P, PP>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, counts);
+    hipLaunchKernelGGL((k_tc_lds<G, CAP, P, PP, WPE>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, counts);
 }
 
 void launch_tc_bin(const Batch &b, const Sched &sc, int force_spill, hipStream_t s)
