@@ -107,6 +107,7 @@ Sched make_sched(char *ws, const Layout &L)
     sc.perm = (int32_t *)(ws + L.perm);
     sc.scr = L.has_scratch ? (uint2 *)(ws + L.scr) : nullptr;
     sc.scnt = L.has_scratch ? (int32_t *)(ws + L.scnt) : nullptr;
+    sc.wstart = (int32_t *)(ws + L.prefix);   // the row-pointer scan's array, idle outside the symbolic phase
     return sc;
 }
 
@@ -274,8 +275,7 @@ spgemm_status run_symbolic(BatchHost &bh, char *ws, int fill, int64_t *nnz_host,
     if (!reuse) launch_compress(bh.batch, s);
     launch_bin(bh.batch, fill ? kModeFill : kModeCount, sc, (int)g_opt.force_spill, nullptr, s);
     if (fill) launch_sym_expand(bh.batch, sc, s);
-    launch_symbolic(bh.batch, sc, fill, choose_group(bh.avg_a), (uint32_t *)(ws + L.spill), L.spill_slots,
-                    L.spill_words, s);
+    launch_symbolic(bh.batch, sc, fill, choose_group(bh.avg_a), s);
     spgemm_status st = check_launch();
     if (st != SPGEMM_OK) return st;
     if (fill) {

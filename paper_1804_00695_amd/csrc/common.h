@@ -91,6 +91,9 @@ struct Sched {
     // and the fill pass expands them instead of recomputing the union
     uint2 *scr;             // nullptr when the workspace has no room for it
     int32_t *scnt;
+    // numeric / adjoint spill path: first window of each spill row (position
+    // in the spill bin), then the total; per-row scratch of na + 1 entries
+    int32_t *wstart;
 };
 
 constexpr int kScratchWords = 64;

@@ -6,12 +6,15 @@
 // W_i goes into an LDS hash (column -> W value); for every entry (i, k) the
 // lanes take distinct entries of B_k, look up W_ij, accumulate W_ij b_kj for
 // dA (group reduction) and add a_ik W_ij into dB with a device fp64 atomic.
-// Rows of W too long for LDS take a workgroup-per-row path that binary-
-// searches W_i in global memory.
+// Rows of W too long for LDS are cut into windows of consecutive positions of
+// W_i, each a task of one wave with its own LDS hash; a window streams the
+// row of A with its rows of B narrowed to the window's column range, and adds
+// its part of dA_ik with a device atomic.
 //
 // Also here: CSR transpose (count, scan, scatter, per-row sort) and a masked
 // gather out[e] = X(row(e), col(e)) over a pattern, used by the unfused
 // per-call adjoint (W B^T masked to pat(A), A^T W masked to pat(B)).
+#include <climits>
 #include <cstdio>
 
 #include "common.h"
@@ -160,39 +163,139 @@ __device__ __forceinline__ int bsearch_w(const MLS_G int32_t *cols, int n, int j
     return (lo < n && cols[lo] == j) ? lo : -1;
 }
 
-// Rows with long W_i: one workgroup per row, W_i searched in global memory;
-// dA is accumulated with atomics (dA was zeroed).
-__global__ __launch_bounds__(kWG) void k_bwd_spill(Batch b, Sched sc, double *dA, double *dB)
+// first position in cols[lo, hi) whose column is >= j
+__device__ __forceinline__ int lower_col_w(const MLS_G int32_t *cols, int lo, int hi, int j)
 {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cols[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+constexpr int kBwdWinCap = 2048;   // table slots of a spill window (CAP / 2 positions of W_i)
+constexpr int kBwdWinBlock = 4;    // consecutive windows a wave takes per counter grab
+
+// Windows of the spill rows come from k_win_scan (same rule: ceil(nnz(W_i) / M)).
+template <int CAP>
+__global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, double *dB)
+{
+    constexpr int G = kWave;
+    constexpr int M = CAP / 2;
+    constexpr int NW = nw_bwd(CAP * 12, 1);
+    __shared__ int s_key[NW * CAP];
+    __shared__ double s_wv[NW * CAP];
+    __shared__ int4 s_par[NW * G];   // staged entries of row i of A: (q0, q1, a)
+
+    const int wave = threadIdx.x >> 6;
+    if (wave >= NW) return;
+    const int lane = threadIdx.x & 63;
+    int *key = s_key + wave * CAP;
+    double *wv = s_wv + wave * CAP;
+    int4 *par = s_par + wave * G;
+
     const Prob P = b.p0;
+    const MLS_G int32_t *__restrict__ arp = gp(P.arp);
     const MLS_G int32_t *__restrict__ aci = gp(P.aci);
     const MLS_G double *__restrict__ aval = gp(P.aval);
     const MLS_G int32_t *__restrict__ brp = gp(P.brp);
     const MLS_G int32_t *__restrict__ bci = gp(P.bci);
     const MLS_G double *__restrict__ bval = gp(P.bval);
+    const MLS_G int32_t *__restrict__ wrp = gp(P.crp);
+    const MLS_G int32_t *__restrict__ wci = gp(P.cci);
+    const MLS_G double *__restrict__ wval = gp(P.cval);
     const int n_bin = gp(sc.bin_count)[kBinSpill];
     const int start = bin_start(sc.bin_count, kBinSpill);
-    for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
-        const int i = bin_row(sc.perm, sc.err, b.na, start + r);
-        if (i < 0) continue;
-        const int w0 = gp(P.crp)[i], nw = gp(P.crp)[i + 1] - w0;
-        const MLS_G int32_t *wc = gp(P.cci) + w0;
-        const MLS_G double *wvv = gp(P.cval) + w0;
-        bool bad = false;
-        for (int p = gp(P.arp)[i]; p < gp(P.arp)[i + 1]; ++p) {
-            const int k = aci[p];
-            const double a = aval[p];
-            double part = 0.0;
-            for (int q = brp[k] + threadIdx.x; q < brp[k + 1]; q += kWG) {
-                int pos = bsearch_w(wc, nw, bci[q]);
-                if (pos < 0) { bad = true; continue; }
-                const double w = wvv[pos];
-                part += w * bval[q];
-                if (dB) atomicAdd(dB + q, a * w);
+    const MLS_G int32_t *wst = gp(sc.wstart);
+    const int nwin = n_bin > 0 ? wst[n_bin] : 0;
+    int32_t *cursor = sc.task_cursor + kBinSpill * kXcd;
+    for (;;) {
+        int u0 = 0;
+        if (lane == 0) u0 = atomicAdd(cursor, 1) * kBwdWinBlock;
+        u0 = __builtin_amdgcn_readlane(u0, 0);
+        if (u0 >= nwin) break;
+        int r = 0;   // largest r with wst[r] <= u0: the row holding window u0
+        {
+            int hi = n_bin - 1;
+            while (r < hi) {
+                const int mid = (r + hi + 1) >> 1;
+                if (wst[mid] <= u0) r = mid; else hi = mid - 1;
             }
-            if (dA && part != 0.0) atomicAdd(dA + p, part);
         }
-        if (bad) atomicOr(sc.err, kErrStructure);
+        const int u1 = min(u0 + kBwdWinBlock, nwin);
+        for (int u = u0; u < u1; ++u) {
+            while (wst[r + 1] <= u) ++r;
+            const int i = bin_row(sc.perm, sc.err, b.na, start + r);
+            if (i < 0) continue;
+            const int nw = gp(sc.val)[i];
+            const int c0 = (u - wst[r]) * M;
+            const int ws0 = wrp[i] + c0;
+            const int n = min(M, nw - c0);
+            const bool narrow = nw > M;
+            // open below for the row's first window and above for its last, so
+            // that a column outside the whole row still fails the lookup
+            const int jlo = c0 == 0 ? INT_MIN : wci[ws0];
+            const int jhi = c0 + n == nw ? INT_MAX : wci[ws0 + n - 1];
+            int logcap = ilog2_ceil(2 * n);
+            if (logcap < 5) logcap = 5;
+            const int cap = 1 << logcap;
+            const uint32_t cmask = (uint32_t)cap - 1u;
+            for (int h = lane; h < cap; h += G) key[h] = -1;
+            bwd_sync();
+            for (int e = lane; e < n; e += G) {
+                const int j = wci[ws0 + e];
+                uint32_t h = hslot((uint32_t)j, logcap);
+                for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                    if (atomicCAS(key + h, -1, j) == -1) { wv[h] = wval[ws0 + e]; break; }
+                    h = (h + 1u) & cmask;
+                }
+            }
+            bwd_sync();
+            bool bad = false;
+            const int ps = arp[i], pe = arp[i + 1];
+            for (int pc = ps; pc < pe; pc += G) {
+                int sq0 = 0, sq1 = 0;
+                double sa = 0.0;
+                if (pc + lane < pe) {
+                    const int k = aci[pc + lane];
+                    sa = aval[pc + lane];
+                    sq0 = brp[k];
+                    sq1 = brp[k + 1];
+                    if (narrow && sq1 - sq0 > 32) {
+                        if (jlo != INT_MIN) sq0 = lower_col_w(bci, sq0, sq1, jlo);
+                        if (jhi != INT_MAX) sq1 = lower_col_w(bci, sq0, sq1, jhi + 1);
+                    }
+                }
+                par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
+                bwd_sync();
+                const int nst = min(G, pe - pc);
+                for (int d0 = 0; d0 < nst; d0 += kBwdUnroll) {
+                    double part[kBwdUnroll];
+#pragma unroll
+                    for (int d = 0; d < kBwdUnroll; ++d) {
+                        part[d] = 0.0;
+                        if (d0 + d >= nst) continue;
+                        const int4 pr = par[d0 + d];
+                        const double a = __hiloint2double(pr.w, pr.z);
+                        for (int q = pr.x + lane; q < pr.y; q += G) {
+                            const int j = bci[q];
+                            if (j < jlo || j > jhi) continue;
+                            double w;
+                            if (!w_lookup(key, wv, logcap, j, w)) { bad = true; continue; }
+                            part[d] += w * bval[q];
+                            if (dB) atomicAdd(dB + q, a * w);
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < kBwdUnroll; ++d) {
+                        const double sum = group_sum<G>(part[d]);
+                        if (dA && lane == 0 && d0 + d < nst && sum != 0.0) atomicAdd(dA + pc + d0 + d, sum);
+                    }
+                }
+                bwd_sync();
+            }
+            if (bad) atomicOr(sc.err, kErrStructure);
+        }
     }
 }
 
@@ -234,9 +337,11 @@ void launch_backward(const Batch &b, const Sched &sc, const double *wval, double
     else launch_bwd_class<32, kFillCap[2]>(b, sc, 2, dA, dB, s);
     launch_bwd_class<64, kFillCap[3]>(b, sc, 3, dA, dB, s);
     launch_bwd_class<64, kFillCap[4]>(b, sc, 4, dA, dB, s);
-    static int spill_grid = device_cu_count();
+    constexpr int NWW = nw_bwd(kBwdWinCap * 12, 1);
+    static int win_grid = bwd_grid(k_bwd_win<kBwdWinCap>, NWW * kWave);
     ProfScope ps("bwd_spill", s);
-    hipLaunchKernelGGL(k_bwd_spill, dim3(spill_grid), dim3(kWG), 0, s, b, sc, dA, dB);
+    hipLaunchKernelGGL(k_win_scan, dim3(1), dim3(kWG), 0, s, b, sc, kBwdWinCap / 2);
+    hipLaunchKernelGGL(k_bwd_win<kBwdWinCap>, dim3(win_grid), dim3(NWW * kWave), 0, s, b, sc, dA, dB);
 }
 
 // ---------------------------------------------------------------------------

@@ -15,10 +15,13 @@
 // a sequential dense-accumulator evaluation bit for bit. Loads for U entries
 // of A are issued before their accumulation steps to hide HBM/L2 latency.
 //
-// Spill path (rows with more than the largest LDS class of outputs): one
-// workgroup per row accumulates directly in C's value array (global memory),
-// locating positions by binary search in C's sorted columns, one k per step
-// with a workgroup barrier between steps.
+// Spill path (rows with more outputs than the largest LDS class holds): the
+// row's outputs are cut into windows of consecutive positions of C, each a
+// task of its own with the LDS table and accumulators of one wave. A window
+// streams the whole row of A, its rows of B narrowed to the window's column
+// range (by binary search in B's sorted columns for long rows, by a range
+// test for short ones); the terms of every c_ij still arrive in ascending k.
+#include <climits>
 #include <cstdio>
 
 #include "common.h"
@@ -28,6 +31,7 @@
 namespace mls {
 
 constexpr int kNumDepth = 4;   // steps whose B loads are issued together
+constexpr int kNumWinCap = 2048;   // table slots of a spill window (CAP / 2 positions)
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -290,60 +294,199 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
     }
 }
 
-__device__ __forceinline__ int bsearch_col(const MLS_G int32_t *cols, int n, int j)
+// first position in cols[lo, hi) whose column is >= j
+__device__ __forceinline__ int lower_col(const MLS_G int32_t *cols, int lo, int hi, int j)
 {
-    int lo = 0, hi = n;
     while (lo < hi) {
-        int mid = (lo + hi) >> 1;
+        const int mid = (lo + hi) >> 1;
         if (cols[mid] < j) lo = mid + 1; else hi = mid;
     }
-    return (lo < n && cols[lo] == j) ? lo : -1;
+    return lo;
 }
 
-__global__ __launch_bounds__(kWG) void k_num_spill(Batch b, Sched sc)
+// Windows of the spill rows: wstart[r] = first window of the r-th row of the
+// spill bin (ceil(nc / m) windows per row), wstart[n] = the total. One
+// workgroup.
+__global__ __launch_bounds__(kWG) void k_win_scan(Batch b, Sched sc, int m)
 {
+    __shared__ int s_red[kWG / kWave];
+    __shared__ int s_carry;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = gp(sc.bin_count)[kBinSpill];
+    const int start = bin_start(sc.bin_count, kBinSpill);
+    MLS_G int32_t *ws = gpw(sc.wstart);
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (int r0 = 0; r0 < n; r0 += kWG) {
+        const int r = r0 + (int)threadIdx.x;
+        int c = 0;
+        if (r < n) {
+            const int g = bin_row(sc.perm, sc.err, b.na, start + r);
+            if (g >= 0) c = (gp(sc.val)[g] + m - 1) / m;
+        }
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        if (lane == kWave - 1) s_red[wave] = incl;
+        __syncthreads();
+        int before = s_carry, all = 0;
+#pragma unroll
+        for (int x = 0; x < kWG / kWave; ++x) {
+            before += x < wave ? s_red[x] : 0;
+            all += s_red[x];
+        }
+        if (r < n) ws[r] = before + incl - c;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ws[n] = s_carry;
+}
+
+constexpr int kWinBlock = 4;   // consecutive windows a wave takes per counter grab
+
+template <int CAP, bool PACK, bool MULTI>
+__global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
+{
+    constexpr int G = kWave;
+    constexpr int M = CAP / 2;   // positions of C per window
+    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK), 1);
+    constexpr int TW = PACK ? CAP : 2 * CAP;
+    __shared__ __attribute__((aligned(16))) uint32_t s_tab[NW * TW];
+    __shared__ double s_acc[NW * M];
+    __shared__ int4 s_par[NW * G];
+
+    const int wave = threadIdx.x >> 6;
+    if (wave >= NW) return;
+    const int lane = threadIdx.x & 63;
+    PosTab<CAP, PACK> tab{s_tab + wave * TW};
+    double *acc = s_acc + wave * M;
+    int4 *par = s_par + wave * G;
+
     const int n_bin = gp(sc.bin_count)[kBinSpill];
     const int start = bin_start(sc.bin_count, kBinSpill);
-    for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
-        const int g = bin_row(sc.perm, sc.err, b.na, start + r);
-        if (g < 0) continue;
-        int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
-        const Prob P = get_prob(b, t);
-        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
-        const int cs = gp(P.crp)[i] - P.c_off;
-        const int nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
-        double *cv = P.cval + cs;
-        const MLS_G int32_t *cc = gp(P.cci) + cs;
-        const MLS_G int32_t *__restrict__ aci = gp(P.aci);
-        const MLS_G double *__restrict__ aval = gp(P.aval);
-        const MLS_G int32_t *__restrict__ brp = gp(P.brp);
-        const MLS_G int32_t *__restrict__ bci = gp(P.bci);
-        const MLS_G double *__restrict__ bval = gp(P.bval);
-        if (!P.accumulate)
-            for (int e = threadIdx.x; e < nc; e += kWG)
-                __hip_atomic_store(cv + e, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        __syncthreads();
-        bool bad = false;
-        const int ps = gp(P.arp)[i] - P.a_off, pe = gp(P.arp)[i + 1] - P.a_off;
-        for (int p = ps; p < pe; ++p) {
-            int k = aci[p];
-            if (k >= P.k_lo && k < P.k_hi) {
-                double a = aval[p];
-                int kl = k - P.k_lo;
-                int q0 = brp[kl] - P.b_off, q1 = brp[kl + 1] - P.b_off;
-                for (int q = q0 + threadIdx.x; q < q1; q += kWG) {
-                    int pos = bsearch_col(cc, nc, bci[q]);
-                    if (pos < 0) { bad = true; continue; }
-                    double old = __hip_atomic_load(cv + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(cv + pos, old + a * bval[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+    const MLS_G int32_t *wst = gp(sc.wstart);
+    const int nwin = n_bin > 0 ? wst[n_bin] : 0;
+    int32_t *cursor = sc.task_cursor + kBinSpill * kXcd;
+    ProbCache pcache;
+    for (;;) {
+        int u0 = 0;
+        if (lane == 0) u0 = atomicAdd(cursor, 1) * kWinBlock;
+        u0 = __builtin_amdgcn_readlane(u0, 0);
+        if (u0 >= nwin) break;
+        int r = 0;   // largest r with wst[r] <= u0: the row holding window u0
+        {
+            int hi = n_bin - 1;
+            while (r < hi) {
+                const int mid = (r + hi + 1) >> 1;
+                if (wst[mid] <= u0) r = mid; else hi = mid - 1;
             }
-            __threadfence();
-            __syncthreads();
         }
-        if (bad) atomicOr(sc.err, kErrStructure);
-        __syncthreads();
+        const int u1 = min(u0 + kWinBlock, nwin);
+        for (int u = u0; u < u1; ++u) {
+            while (wst[r + 1] <= u) ++r;
+            const int g = bin_row(sc.perm, sc.err, b.na, start + r);
+            if (g < 0) continue;
+            int t = 0, i = g;
+            if (MULTI) {
+                t = find_prob_cached(b.abase, b.nprob, g, pcache);
+                i = g - pcache.lo;
+            }
+            const Prob P = prob_of<MULTI>(b, t);
+            const MLS_G int32_t *__restrict__ aci = gp(P.aci);
+            const MLS_G double *__restrict__ aval = gp(P.aval);
+            const MLS_G int32_t *__restrict__ brp = gp(P.brp);
+            const MLS_G int32_t *__restrict__ bci = gp(P.bci);
+            const MLS_G double *__restrict__ bval = gp(P.bval);
+            const MLS_G int32_t *__restrict__ cci = gp(P.cci);
+            MLS_G double *__restrict__ cval = gpw(P.cval);
+            const int b_off = P.b_off, k_lo = P.k_lo, k_hi = P.k_hi;
+            const bool accumulate = P.accumulate != 0;
+            const int nc = gp(sc.val)[g];
+            const int c0 = (u - wst[r]) * M;   // first position of the window in the row
+            const int cs = gp(P.crp)[i] - P.c_off + c0;
+            const int n = min(M, nc - c0);
+            const int ps = gp(P.arp)[i] - P.a_off, pe = gp(P.arp)[i + 1] - P.a_off;
+            const bool narrow = nc > M;
+            // columns the window takes: from its first to its last column, open
+            // below for the row's first window and above for its last, so that
+            // a column outside the whole row still fails the lookup
+            const int jlo = c0 == 0 ? INT_MIN : cci[cs];
+            const int jhi = c0 + n == nc ? INT_MAX : cci[cs + n - 1];
+            int logcap = ilog2_ceil(2 * n);
+            if (logcap < 5) logcap = 5;
+            tab.clear(1 << logcap, lane, G);
+            nwave_sync();
+            for (int e = lane; e < n; e += G) {
+                tab.insert(logcap, cci[cs + e], e);
+                acc[e] = accumulate ? cval[cs + e] : 0.0;
+            }
+            nwave_sync();
+            bool bad = false;
+            for (int pc = ps; pc < pe; pc += G) {
+                // stage the chunk: (q0, q1, a) of entry pc + lane, the row of B
+                // narrowed to the window's columns when it is long
+                int sq0 = 0, sq1 = 0;
+                double sa = 0.0;
+                if (pc + lane < pe) {
+                    const int ka = aci[pc + lane];
+                    sa = aval[pc + lane];
+                    if (ka >= k_lo && ka < k_hi) {
+                        sq0 = brp[ka - k_lo] - b_off;
+                        sq1 = brp[ka - k_lo + 1] - b_off;
+                        if (narrow && sq1 - sq0 > 32) {
+                            if (jlo != INT_MIN) sq0 = lower_col(bci, sq0, sq1, jlo);
+                            if (jhi != INT_MAX) sq1 = lower_col(bci, sq0, sq1, jhi + 1);
+                        }
+                    }
+                }
+                par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
+                nwave_sync();
+                const int nst = min(G, pe - pc);
+                for (int u0s = 0; u0s < nst; u0s += kNumDepth) {
+                    int jv[kNumDepth];
+                    double bv[kNumDepth], av[kNumDepth];
+                    uint32_t longm = 0;
+#pragma unroll
+                    for (int d = 0; d < kNumDepth; ++d) {
+                        jv[d] = -1; bv[d] = 0.0; av[d] = 0.0;
+                        if (u0s + d < nst) {
+                            const int4 pr = par[u0s + d];
+                            av[d] = __hiloint2double(pr.w, pr.z);
+                            if (pr.y - pr.x > G) longm |= 1u << d;
+                            const int q = pr.x + lane;
+                            if (q < pr.y) { jv[d] = bci[q]; bv[d] = bval[q]; }
+                        }
+                    }
+                    int posv[kNumDepth];
+#pragma unroll
+                    for (int d = 0; d < kNumDepth; ++d)
+                        posv[d] = (jv[d] >= 0 && jv[d] >= jlo && jv[d] <= jhi) ? tab.lookup(logcap, jv[d]) : -2;
+#pragma unroll
+                    for (int d = 0; d < kNumDepth; ++d) {
+                        if (posv[d] >= 0) atomicAdd(acc + posv[d], av[d] * bv[d]);
+                        else if (posv[d] == -1) bad = true;
+                        if ((longm >> d) & 1u) {
+                            const int4 pr = par[u0s + d];
+                            for (int q = pr.x + G + lane; q < pr.y; q += G) {
+                                const int j = bci[q];
+                                if (j < jlo || j > jhi) continue;
+                                const int pos = tab.lookup(logcap, j);
+                                if (pos >= 0) atomicAdd(acc + pos, av[d] * bval[q]);
+                                else bad = true;
+                            }
+                        }
+                    }
+                }
+                nwave_sync();
+            }
+            if (bad) atomicOr(sc.err, kErrStructure);
+            for (int e = lane; e < n; e += G) cval[cs + e] = acc[e];
+            nwave_sync();
+        }
     }
 }
 
@@ -388,6 +531,31 @@ static void launch_num_class(const Batch &b, const Sched &sc, int bin, hipStream
         launch_num_multi<G, CAP, false>(b, sc, bin, s);
 }
 
+template <int CAP, bool PACK, bool MULTI>
+static void launch_num_win(const Batch &b, const Sched &sc, hipStream_t s)
+{
+    constexpr int NW = nw_num(num_row_bytes(CAP, kWave, PACK), 1);
+    static int grid = persistent_grid_n(k_num_win<CAP, PACK, MULTI>, NW * kWave);
+    static char name[64];
+    if (!name[0]) snprintf(name, sizeof(name), "num_spill_C%d%s%s", CAP, PACK ? "_p" : "", MULTI ? "_b" : "");
+    ProfScope ps(name, s);
+    hipLaunchKernelGGL(k_win_scan, dim3(1), dim3(kWG), 0, s, b, sc, CAP / 2);
+    hipLaunchKernelGGL((k_num_win<CAP, PACK, MULTI>), dim3(grid), dim3(NW * kWave), 0, s, b, sc);
+}
+
+static void launch_num_spill(const Batch &b, const Sched &sc, hipStream_t s)
+{
+    constexpr int CAP = kNumWinCap;
+    const bool pack = b.max_ncols > 0 && (uint32_t)b.max_ncols <= PackBits<CAP>::kMaxCols;
+    if (b.nprob > 1) {
+        if (pack) launch_num_win<CAP, true, true>(b, sc, s);
+        else launch_num_win<CAP, false, true>(b, sc, s);
+    } else {
+        if (pack) launch_num_win<CAP, true, false>(b, sc, s);
+        else launch_num_win<CAP, false, false>(b, sc, s);
+    }
+}
+
 void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s)
 {
     if (b.na <= 0) return;
@@ -402,9 +570,7 @@ void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s)
     else launch_num_class<32, kFillCap[2]>(b, sc, 2, s);
     launch_num_class<64, kFillCap[3]>(b, sc, 3, s);
     launch_num_class<64, kFillCap[4]>(b, sc, 4, s);
-    static int spill_grid = device_cu_count();
-    ProfScope ps("num_spill", s);
-    hipLaunchKernelGGL(k_num_spill, dim3(spill_grid), dim3(kWG), 0, s, b, sc);
+    launch_num_spill(b, sc, s);
 }
 
 }  // namespace mls

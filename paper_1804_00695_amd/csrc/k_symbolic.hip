@@ -315,93 +315,171 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 
     }
 }
 
-// Spill path: one workgroup per row, dense bitmap in global memory.
-__global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, uint32_t *bitmaps,
-                                                   int64_t words)
+// Spill path: rows whose word bound exceeds the largest LDS class. One
+// workgroup per row, rows taken from a counter. The row's union is a dense
+// bitmap in LDS over a window of columns: the whole column range whenever it
+// fits (up to 2^20 columns with 128 KB), else one window after the other,
+// each entry's words narrowed to the window by binary search (a row of
+// comp(B) lists its sets in ascending order). The words of the staged
+// entries are cut into pieces of kSpillPW, dealt to the threads round-robin,
+// so that one long row of B does not hold up the workgroup; OR-ing is order-
+// free. The fill pass reads the bitmap back in column order.
+constexpr int kSpillPW = 4;
+
+__device__ __forceinline__ int lower_set(const MLS_G u32x2 *w, int n, uint32_t set)
 {
+    // first word of w[0, n) whose set is >= set
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (w[mid].x < set) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, int win_words)
+{
+    extern __shared__ uint32_t s_bm[];   // win_words words
+    __shared__ int s_poff[kWG + 1];
+    __shared__ int s_st[kWG];
+    __shared__ int s_nk[kWG];
     __shared__ int s_red[kWG / kWave];
-    __shared__ int s_base;
-    uint32_t *bm = bitmaps + (int64_t)blockIdx.x * words;
+    __shared__ int s_row;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n_bin = gp(sc.bin_count)[kBinSpill];
     const int start = bin_start(sc.bin_count, kBinSpill);
-    for (int r = blockIdx.x; r < n_bin; r += gridDim.x) {
+    int32_t *cursor = sc.task_cursor + kBinSpill * kXcd;
+    for (;;) {
+        if (tid == 0) s_row = atomicAdd(cursor, 1);
+        __syncthreads();
+        const int r = s_row;
+        __syncthreads();
+        if (r >= n_bin) break;
         const int g = bin_row(sc.perm, sc.err, b.na, start + r);
         if (g < 0) continue;
-        int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
+        const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
         const Prob P = get_prob(b, t);
-        int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
+        const MLS_G int32_t *__restrict__ aci = gp(P.aci);
+        const MLS_G int32_t *__restrict__ brp = gp(P.brp);
+        const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
+        const MLS_G u32x2 *__restrict__ bw = (const MLS_G u32x2 *)P.bw;
         const int nwords = (P.ncols + 31) >> 5;
-        for (int w = threadIdx.x; w < nwords; w += kWG)
-            __hip_atomic_store(bm + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        __syncthreads();
-        int ps = gp(P.arp)[i] - P.a_off, pe = gp(P.arp)[i + 1] - P.a_off;
-        for (int p = ps + threadIdx.x; p < pe; p += kWG) {
-            int k = gp(P.aci)[p];
-            if (k < P.k_lo || k >= P.k_hi) continue;
-            int kl = k - P.k_lo;
-            const MLS_G u32x2 *wv = (const MLS_G u32x2 *)P.bw + (gp(P.brp)[kl] - P.b_off);
-            int nw = gp(P.bwc)[kl];
-            for (int x = 0; x < nw; ++x) {
-                u32x2 wd = wv[x];
-                atomicOr(bm + wd.x, wd.y);
-            }
-        }
-        __threadfence();
-        __syncthreads();
-        if (!fill) {
-            int c = 0;
-            for (int w = threadIdx.x; w < nwords; w += kWG)
-                c += __popc(__hip_atomic_load(bm + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            c = group_sum<kWave>(c);
-            if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = c;
+        const int ww = nwords < win_words ? nwords : win_words;
+        const bool windowed = ww < nwords;
+        const int ps = gp(P.arp)[i] - P.a_off, pe = gp(P.arp)[i + 1] - P.a_off;
+        const int cs = fill ? gp(P.crp)[i] - P.c_off : 0;
+        const int ce = fill ? gp(P.crp)[i + 1] - P.c_off : 0;
+        int total = 0;   // columns found so far (uniform)
+        bool bad = false;
+        for (int w0 = 0; w0 < nwords; w0 += ww) {
+            const int wn = nwords - w0 < ww ? nwords - w0 : ww;
+            for (int x = tid; x < wn; x += kWG) s_bm[x] = 0u;
             __syncthreads();
-            if (threadIdx.x == 0) {
-                int s = 0;
-                for (int x = 0; x < kWG / kWave; ++x) s += s_red[x];
-                gpw(sc.val)[g] = s;
-                if (sc.scr) gpw(sc.scnt)[g] = -1;   // recomputed by the fill pass
-            }
-            __syncthreads();
-        } else {
-            int cs = gp(P.crp)[i] - P.c_off;
-            MLS_G int32_t *cci = gpw(P.cci);
-            if (threadIdx.x == 0) s_base = 0;
-            __syncthreads();
-            for (int w0 = 0; w0 < nwords; w0 += kWG) {
-                int w = w0 + threadIdx.x;
-                uint32_t m = w < nwords ? __hip_atomic_load(bm + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-                int c = __popc(m);
-                // exclusive scan of c over the workgroup
-                int lane = threadIdx.x & 63;
-                int incl = c;
-                for (int o = 1; o < 64; o <<= 1) {
-                    int y = __shfl_up(incl, o, kWave);
+            for (int pb = ps; pb < pe; pb += kWG) {
+                int st = 0, nk = 0;
+                const int p = pb + tid;
+                if (p < pe) {
+                    const int k = aci[p];
+                    if (k >= P.k_lo && k < P.k_hi) {
+                        const int kl = k - P.k_lo;
+                        st = brp[kl] - P.b_off;
+                        nk = bwc[kl];
+                        if (windowed) {
+                            const int lo = lower_set(bw + st, nk, (uint32_t)w0);
+                            const int hi = lower_set(bw + st, nk, (uint32_t)(w0 + wn));
+                            st += lo;
+                            nk = hi - lo;
+                        }
+                    }
+                }
+                // exclusive scan of the piece counts over the workgroup
+                const int np = (nk + kSpillPW - 1) / kSpillPW;
+                int incl = np;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int y = __shfl_up(incl, o, kWave);
                     if (lane >= o) incl += y;
                 }
-                if (lane == 63) s_red[threadIdx.x >> 6] = incl;
+                if (lane == kWave - 1) s_red[wave] = incl;
                 __syncthreads();
-                int off = s_base;
-                for (int x = 0; x < (int)(threadIdx.x >> 6); ++x) off += s_red[x];
-                int pos = cs + off + incl - c;
-                const int ce = gp(P.crp)[i + 1] - P.c_off;
-                while (m) {
-                    int bit = __ffs(m) - 1;
-                    if (pos < ce) cci[pos] = w * 32 + bit;
-                    else atomicOr(sc.err, kErrStructure);
-                    ++pos;
-                    m &= m - 1u;
+                int before = 0, all = 0;
+#pragma unroll
+                for (int x = 0; x < kWG / kWave; ++x) {
+                    before += x < wave ? s_red[x] : 0;
+                    all += s_red[x];
                 }
+                s_poff[tid] = before + incl - np;
+                s_st[tid] = st;
+                s_nk[tid] = nk;
+                if (tid == 0) s_poff[kWG] = all;
                 __syncthreads();
-                if (threadIdx.x == 0) {
-                    int s = 0;
-                    for (int x = 0; x < kWG / kWave; ++x) s += s_red[x];
-                    s_base += s;
+                for (int q = tid; q < all; q += kWG) {
+                    int lo = 0, hi = kWG - 1;   // largest e with s_poff[e] <= q
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_poff[mid] <= q) lo = mid; else hi = mid - 1;
+                    }
+                    const int first = (q - s_poff[lo]) * kSpillPW;
+                    const int len = min(kSpillPW, s_nk[lo] - first);
+                    const MLS_G u32x2 *src = bw + s_st[lo] + first;
+                    u32x2 wd[kSpillPW];
+#pragma unroll
+                    for (int d = 0; d < kSpillPW; ++d)
+                        if (d < len) wd[d] = src[d];
+#pragma unroll
+                    for (int d = 0; d < kSpillPW; ++d) {
+                        if (d >= len) continue;
+                        const uint32_t x = wd[d].x - (uint32_t)w0;
+                        if (x < (uint32_t)wn) atomicOr(s_bm + x, wd[d].y);
+                        else bad = true;
+                    }
                 }
                 __syncthreads();
             }
+            // the window's columns: thread tid reads a run of consecutive words
+            const int run = (wn + kWG - 1) / kWG;
+            const int x0 = tid * run;
+            const int x1 = x0 + run < wn ? x0 + run : wn;
+            int c = 0;
+            for (int x = x0; x < x1; ++x) c += __popc(s_bm[x]);
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += y;
+            }
+            if (lane == kWave - 1) s_red[wave] = incl;
+            __syncthreads();
+            int before = 0, all = 0;
+#pragma unroll
+            for (int x = 0; x < kWG / kWave; ++x) {
+                before += x < wave ? s_red[x] : 0;
+                all += s_red[x];
+            }
+            if (fill) {
+                MLS_G int32_t *cci = gpw(P.cci);
+                int pos = cs + total + before + incl - c;
+                for (int x = x0; x < x1; ++x) {
+                    uint32_t m = s_bm[x];
+                    while (m) {
+                        const int bit = __ffs(m) - 1;
+                        if (pos < ce) cci[pos] = (w0 + x) * 32 + bit;
+                        else bad = true;
+                        ++pos;
+                        m &= m - 1u;
+                    }
+                }
+            }
+            total += all;
+            __syncthreads();
         }
-        __syncthreads();
+        if (bad) atomicOr(sc.err, kErrStructure);
+        if (!fill && tid == 0) {
+            gpw(sc.val)[g] = total;
+            if (sc.scr) gpw(sc.scnt)[g] = -1;   // recomputed by the fill pass
+        }
+        if (fill && tid == 0 && cs + total != ce) atomicOr(sc.err, kErrStructure);
     }
 }
 
@@ -632,14 +710,34 @@ static void launch_sym_all(const Batch &b, const Sched &sc, int G, hipStream_t s
     launch_sym_class<64, C4, FILL>(b, sc, 4, s);
 }
 
-void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, uint32_t *spill_bitmaps, int spill_slots,
-                     int64_t spill_words, hipStream_t s)
+void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, hipStream_t s)
 {
     if (b.na <= 0) return;
     if (fill) launch_sym_all<true>(b, sc, G, s);
     else launch_sym_all<false>(b, sc, G, s);
+    // bitmap window: every column of C when known and small, else the most the
+    // workgroup's LDS holds next to the kernel's own arrays (at most 2^15 words)
+    static int max_words = [] {
+        int w = (device_max_lds() - 8192) / 4;
+        return w < 4096 ? 4096 : (w > 32768 ? 32768 : w);
+    }();
+    int win = max_words;
+    if (b.max_ncols > 0) {
+        const int need = (b.max_ncols + 31) / 32;
+        if (need < win) win = need < 64 ? 64 : need;
+    }
+    const int grid = spill_grid(k_sym_spill, win * 4);
     ProfScope ps(fill ? "sym_fill_spill" : "sym_count_spill", s);
-    hipLaunchKernelGGL(k_sym_spill, dim3(spill_slots), dim3(kWG), 0, s, b, sc, fill, spill_bitmaps, spill_words);
+    hipLaunchKernelGGL(k_sym_spill, dim3(grid), dim3(kWG), (size_t)win * 4, s, b, sc, fill, win);
+}
+
+int device_max_lds()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || n <= 0)
+        return 65536;
+    return n;
 }
 
 int device_cu_count()

@@ -21,13 +21,15 @@ void launch_scan(const int32_t *val, int n, int64_t *tile_sum, int64_t *prefix, 
 void launch_write_rowptr(const Batch &b, const int64_t *prefix, int64_t *totals, uint32_t *err, hipStream_t s);
 
 // Symbolic phase: count (fill == 0) or fill (fill == 1) over the binned rows.
-// G = lanes per row for the LDS classes. spill_bitmaps: global scratch of
-// spill_slots bitmaps of spill_words 32-bit words each.
-void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, uint32_t *spill_bitmaps,
-                     int spill_slots, int64_t spill_words, hipStream_t s);
+// G = lanes per row for the LDS classes.
+void launch_symbolic(const Batch &b, const Sched &sc, int fill, int G, hipStream_t s);
 
 // Fill pass from the count pass's scratch words (rows with scnt >= 0).
 void launch_sym_expand(const Batch &b, const Sched &sc, hipStream_t s);
+
+// Windows of the spill bin's rows, ceil(size / m) per row: sc.wstart[r] = the
+// first window of the r-th spill row, sc.wstart[n] = their total (one workgroup).
+__global__ void k_win_scan(Batch b, Sched sc, int m);
 
 // Numeric phase (row-range fused multiply-add) over the binned rows.
 void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s);
@@ -51,5 +53,18 @@ void launch_mask_gather(int32_t nrows, const int32_t *xrp, const int32_t *xci, c
 
 // Persistent grid sizes (workgroups) per kernel shape.
 int device_cu_count();
+int device_max_lds();   // LDS bytes one workgroup may allocate
+
+// Workgroups of a persistent grid: resident workgroups per CU times the CUs,
+// for a kernel of kWG threads with `smem` bytes of dynamic LDS.
+template <typename K>
+inline int spill_grid(K kernel, int smem)
+{
+    static int cus = device_cu_count();
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWG, (size_t)smem) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
 
 }  // namespace mls

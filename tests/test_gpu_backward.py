@@ -100,3 +100,17 @@ def test_autograd_gradcheck_tiny():
     C = mls.symbolic(dA_, dB_, with_values=False)
     f = lambda a, b: mls.SpGEMMFn.apply(a, b, dA_, dB_, C)
     assert torch.autograd.gradcheck(f, (av, bv), eps=1e-6, atol=1e-8)
+
+
+def test_rmat_power_law_spill():
+    # adjoint of A*A for a power-law graph: rows of W up to ~2800 entries (two
+    # spill windows) next to short rows, hub rows of B narrowed per window
+    G = synth.rmat_graph(12, 8, seed=5)
+    A = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), 8))
+    C, _ = oracle.spgemm(A, A, with_abs=False)
+    assert np.diff(C.row_ptr).max() > 2048
+    W = synth.Csr(C.nrows, C.ncols, C.row_ptr, C.col_idx, synth.normal_values(C.nnz, 9))
+    dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(W))
+    rA, rB, aA, aB = oracle.backward(A, A, W)
+    assert np.all(np.abs(dA.cpu().numpy() - rA) <= TOL * aA + 1e-300)
+    assert np.all(np.abs(dB.cpu().numpy() - rB) <= TOL * aB + 1e-300)

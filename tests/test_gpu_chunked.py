@@ -29,6 +29,7 @@ def run_chunked(A, B, R, budget, nbuf, min_parts):
 CASES = [
     ("stencil", 12, 4.0), ("stencil", 12, 0.5), ("stencil", 12, 0.15), ("stencil", 12, 0.05),
     ("poisson", 0, 3.0), ("poisson", 0, 0.3), ("poisson", 0, 0.08),
+    ("rmat", 12, 0.3),   # rows of C past the LDS classes: spill windows on B's row parts
 ]
 
 
@@ -38,6 +39,10 @@ def test_chunked_bitwise(case, nbuf, min_parts):
     kind, n, frac = case
     if kind == "stencil":
         A = synth.stencil27_3d(n, amp=0.1)
+        B = A
+    elif kind == "rmat":
+        G = synth.rmat_graph(n, 8, seed=5)
+        A = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), 8))
         B = A
     else:
         A = synth.poisson_csr(3000, 2500, 6.0, 41)

@@ -330,3 +330,28 @@ def test_symbolic_fill_paths(mode):
             kw["fill_twice"] = True
         rp, ci = raw_symbolic(X, Y, **kw)
         assert np.array_equal(rp, R.row_ptr) and np.array_equal(ci, R.col_idx)
+
+
+def test_spill_column_windows():
+    # rows of C with ~12k entries spread over 3M columns: the spill bitmap
+    # covers the columns in several windows, each entry's words narrowed to
+    # the window; also a batch row of C whose columns are all in the last window
+    A = wide_rows(6, 5000, 3000, 31)
+    B = synth.poisson_csr(5000, 3_000_000, 4.0, 32)
+    check(A, B)
+    g = synth.rng(33)
+    rp = np.arange(0, 4 * 5001, 4, dtype=np.int32)
+    ci = np.sort(g.integers(2_990_000, 3_000_000, (5000, 4)), axis=1).astype(np.int32)
+    ci[:, 1:] += np.cumsum(ci[:, 1:] == ci[:, :-1], axis=1).astype(np.int32)   # keep each row strictly rising
+    B2 = synth.Csr(5000, 3_000_010, rp, ci.ravel(), g.standard_normal(ci.size))
+    check(A, B2)
+
+
+def test_rmat_power_law_spill():
+    # A*A for a power-law graph (R-MAT scale 13): ~1300 rows of C hold more
+    # than 2048 entries (up to ~5400, three spill windows), long rows of B
+    # (hubs) are narrowed to each window by binary search
+    G = synth.rmat_graph(13, 8, seed=5)
+    A = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), 8))
+    R = check(A, A)
+    assert np.diff(R.row_ptr).max() > 4096
