@@ -320,6 +320,32 @@ def bench_backward(torch, mls, synth):
     return res
 
 
+def bench_power_law(torch, mls, synth):
+    """C = A*A and its adjoint for a power-law matrix (R-MAT scale 16, edge
+    factor 8, seed 5, symmetric, N(0,1) values): most multiply-adds fall in
+    rows of C past the LDS classes, i.e. on the spill paths."""
+    G = synth.rmat_graph(16, 8, seed=5)
+    A = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), 8))
+    dA = mls.DeviceCsr.from_host(A)
+    ws = mls.Workspace()
+    C = mls.symbolic(dA, dA, ws)
+    torch.cuda.synchronize()
+    _, madds = mls.row_work(dA, dA, ws)
+    lens = torch.diff(C.row_ptr.long())
+    spill_rows = int((lens > 2048).sum().item())
+    W = mls.DeviceCsr(C.nrows, C.ncols, C.row_ptr, C.col_idx,
+                      torch.from_numpy(synth.normal_values(C.nnz, 9)).cuda())
+    t_s, _ = timed(torch, lambda: mls.symbolic(dA, dA, ws), 3)
+    t_n, _ = timed(torch, lambda: mls.numeric(dA, dA, C, ws), 3)
+    t_b, _ = timed(torch, lambda: mls.backward(dA, dA, W, ws=ws), 3)
+    res = {"workload": "R-MAT scale 16, edge factor 8, seed 5, C = A*A", "rows": A.nrows, "nnz_A": A.nnz,
+           "nnz_C": int(C.nnz), "multiply_adds": int(madds), "rows_of_C_past_LDS_classes": spill_rows,
+           "symbolic_ms": round(t_s, 3), "numeric_ms": round(t_n, 3), "backward_ms": round(t_b, 3),
+           "numeric_gflops": round(2 * madds / (t_n * 1e-3) / 1e9, 1)}
+    log(f"power law: {res}")
+    return res
+
+
 def tc_word_model(n, lrp, lci):
     """Compressed-word accounting of (L * comp(L)) o L from L's structure:
     words of each row (distinct col >> 5), the word operations (for every
@@ -543,6 +569,12 @@ def main():
             extras["backward"] = bench_backward(torch, mls, synth)
         except Exception as e:
             extras["backward"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        log("power law")
+        try:
+            extras["power_law"] = bench_power_law(torch, mls, synth)
+        except Exception as e:
+            extras["power_law"] = {"error": repr(e)}
         result["extras"] = extras
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(A)

@@ -253,6 +253,8 @@ __device__ __forceinline__ int class_of(int mode, int64_t size, int force_spill)
 
 constexpr int kBinRG = 8;                    // lanes per row where the size is gathered
 constexpr int kBinSlots = kWG / kBinRG;      // rows in flight per workgroup
+constexpr int kBinLongRow = 512;             // rows of A longer than this are gathered by the workgroup
+constexpr int kBinMaxLong = 64;              // such rows deferred per block (more are gathered in place)
 
 // Per-block bin counts (LDS) written to blk_cnt[c * nblk + block].
 __device__ __forceinline__ void bin_write_counts(const Sched &sc, const int *cnt)
@@ -260,13 +262,49 @@ __device__ __forceinline__ void bin_write_counts(const Sched &sc, const int *cnt
     if (threadIdx.x < kNumBins) gpw(sc.blk_cnt)[threadIdx.x * sc.nblk + (int)blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Bin of a row of known size (count, fill and work modes), by one thread.
+__device__ __forceinline__ void bin_place(int mode, const Sched &sc, int force_spill, const Prob &P, int g, int i,
+                                          bool from_scratch, int64_t size, int *cnt, unsigned long long *tsum)
+{
+    int c;
+    if (from_scratch) {
+        c = kBinEmpty;
+    } else {
+        if (mode == kModeFill) {
+            const int64_t nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
+            size = size < nc ? size : nc;
+        }
+        if (mode == kModeWork) {
+            c = kBinEmpty;
+            if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
+            atomicAdd(tsum, (unsigned long long)size);
+        } else {
+            c = class_of(mode, size, force_spill);
+            // a large row whose dense bitmap over C's columns is at most half
+            // its class table takes the spill path's LDS bitmap instead
+            if (c >= 3 && c < kNumClasses &&
+                (int64_t)P.ncols <= 32 * (int64_t)(mode == kModeCount ? kCountCap[c] : kFillCap[c]))
+                c = kBinSpill;
+            // rows without work get no symbolic kernel: their scratch is empty
+            if (mode == kModeCount && sc.scr && c == kBinEmpty) gpw(sc.scnt)[g] = 0;
+        }
+    }
+    if (size >= 0x7fffffffLL) size = 0x7fffffff;
+    gpw(sc.val)[g] = (int32_t)size;
+    gpw(sc.cls)[g] = (uint8_t)c;
+    atomicAdd(&cnt[c], 1);
+}
+
 __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int force_spill,
                                              unsigned long long *total)
 {
     __shared__ int cnt[kNumBins];
     __shared__ unsigned long long tsum;
+    __shared__ int s_long[kBinMaxLong];
+    __shared__ int s_nlong;
+    __shared__ int64_t s_red[kWG / kWave];
     if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) tsum = 0;
+    if (threadIdx.x == 0) { tsum = 0; s_nlong = 0; }
     __syncthreads();
     const int g0 = blockIdx.x * kBinRowsPerWG;
     ProbCache pc;
@@ -298,11 +336,21 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
         const bool from_scratch = mode == kModeFill && sc.scr && gp(sc.scnt)[g] >= 0;
         int64_t size = 0;
         if (!from_scratch) {
+            const int s = gp(P.arp)[i] - P.a_off, e = gp(P.arp)[i + 1] - P.a_off;
+            if (e - s > kBinLongRow) {
+                // long row: gathered below by the whole workgroup, unless the list is full
+                int at = 0;
+                if (lane == 0) {
+                    at = atomicAdd(&s_nlong, 1);
+                    if (at < kBinMaxLong) s_long[at] = r;
+                }
+                at = __shfl(at, 0, kBinRG);
+                if (at < kBinMaxLong) continue;
+            }
             const MLS_G int32_t *__restrict__ aci = gp(P.aci);
             const MLS_G int32_t *__restrict__ brp = gp(P.brp);
             const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
             const int k_lo = P.k_lo, k_hi = P.k_hi;
-            const int s = gp(P.arp)[i] - P.a_off, e = gp(P.arp)[i + 1] - P.a_off;
             for (int p = s + lane; p < e; p += kBinRG) {
                 const int k = aci[p];
                 if (k < k_lo || k >= k_hi) continue;
@@ -311,32 +359,37 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
             }
             size = group_sum<kBinRG>(size);
         }
-        if (lane == 0) {
-            int c;
-            if (from_scratch) {
-                c = kBinEmpty;
-            } else {
-                if (mode == kModeFill) {
-                    const int64_t nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
-                    size = size < nc ? size : nc;
-                }
-                if (mode == kModeWork) {
-                    c = kBinEmpty;
-                    if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
-                    atomicAdd(&tsum, (unsigned long long)size);
-                } else {
-                    c = class_of(mode, size, force_spill);
-                    // rows without work get no symbolic kernel: their scratch is empty
-                    if (mode == kModeCount && sc.scr && c == kBinEmpty) gpw(sc.scnt)[g] = 0;
-                }
-            }
-            if (size >= 0x7fffffffLL) size = 0x7fffffff;
-            gpw(sc.val)[g] = (int32_t)size;
-            gpw(sc.cls)[g] = (uint8_t)c;
-            atomicAdd(&cnt[c], 1);
-        }
+        if (lane == 0) bin_place(mode, sc, force_spill, P, g, i, from_scratch, size, cnt, &tsum);
     }
     __syncthreads();
+    // the deferred long rows, one at a time across the workgroup
+    const int nlong = s_nlong < kBinMaxLong ? s_nlong : kBinMaxLong;
+    for (int x = 0; x < nlong; ++x) {
+        const int g = g0 + s_long[x];
+        const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
+        const Prob P = get_prob(b, t);
+        const int i = g - (b.nprob == 1 ? 0 : pc.lo);
+        const MLS_G int32_t *__restrict__ aci = gp(P.aci);
+        const MLS_G int32_t *__restrict__ brp = gp(P.brp);
+        const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
+        const int s = gp(P.arp)[i] - P.a_off, e = gp(P.arp)[i + 1] - P.a_off;
+        int64_t size = 0;
+        for (int p = s + (int)threadIdx.x; p < e; p += kWG) {
+            const int k = aci[p];
+            if (k < P.k_lo || k >= P.k_hi) continue;
+            const int kl = k - P.k_lo;
+            size += mode == kModeWork ? (int64_t)(brp[kl + 1] - brp[kl]) : (int64_t)bwc[kl];
+        }
+        size = group_sum<kWave>(size);
+        if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = size;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t tot = 0;
+            for (int w = 0; w < kWG / kWave; ++w) tot += s_red[w];
+            bin_place(mode, sc, force_spill, P, g, i, false, tot, cnt, &tsum);
+        }
+        __syncthreads();
+    }
     bin_write_counts(sc, cnt);
     if (threadIdx.x == 0 && total && tsum) atomicAdd(total, tsum);
 }

@@ -355,3 +355,15 @@ def test_rmat_power_law_spill():
     A = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), 8))
     R = check(A, A)
     assert np.diff(R.row_ptr).max() > 4096
+
+
+def test_many_long_rows_in_one_block():
+    # 100 rows of 600 entries in one binning block: 64 are sized by the whole
+    # workgroup, the rest in place; sizes feed both the bins and row_work
+    A = wide_rows(100, 5000, 600, 41)
+    B = synth.poisson_csr(5000, 9000, 3.0, 42)
+    check(A, B)
+    w, madds = mls.row_work(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B))
+    per_entry = np.diff(B.row_ptr)[A.col_idx]
+    ref = np.add.reduceat(per_entry, A.row_ptr[:-1]).astype(np.int64)
+    assert np.array_equal(w.cpu().numpy(), ref) and madds == int(ref.sum())
