@@ -31,7 +31,8 @@
 namespace mls {
 
 constexpr int kNumDepth = 4;   // steps whose B loads are issued together
-constexpr int kNumWinCap = 2048;   // table slots of a spill window (CAP / 2 positions)
+constexpr int kNumWinCap = 1024;   // table slots of a spill window (CAP / 2 positions)
+constexpr int kWinDepth = 8;       // spill window: steps whose B loads are issued together
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -446,12 +447,12 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
                 par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
                 nwave_sync();
                 const int nst = min(G, pe - pc);
-                for (int u0s = 0; u0s < nst; u0s += kNumDepth) {
-                    int jv[kNumDepth];
-                    double bv[kNumDepth], av[kNumDepth];
+                for (int u0s = 0; u0s < nst; u0s += kWinDepth) {
+                    int jv[kWinDepth];
+                    double bv[kWinDepth], av[kWinDepth];
                     uint32_t longm = 0;
 #pragma unroll
-                    for (int d = 0; d < kNumDepth; ++d) {
+                    for (int d = 0; d < kWinDepth; ++d) {
                         jv[d] = -1; bv[d] = 0.0; av[d] = 0.0;
                         if (u0s + d < nst) {
                             const int4 pr = par[u0s + d];
@@ -461,12 +462,12 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
                             if (q < pr.y) { jv[d] = bci[q]; bv[d] = bval[q]; }
                         }
                     }
-                    int posv[kNumDepth];
+                    int posv[kWinDepth];
 #pragma unroll
-                    for (int d = 0; d < kNumDepth; ++d)
+                    for (int d = 0; d < kWinDepth; ++d)
                         posv[d] = (jv[d] >= 0 && jv[d] >= jlo && jv[d] <= jhi) ? tab.lookup(logcap, jv[d]) : -2;
 #pragma unroll
-                    for (int d = 0; d < kNumDepth; ++d) {
+                    for (int d = 0; d < kWinDepth; ++d) {
                         if (posv[d] >= 0) atomicAdd(acc + posv[d], av[d] * bv[d]);
                         else if (posv[d] == -1) bad = true;
                         if ((longm >> d) & 1u) {
