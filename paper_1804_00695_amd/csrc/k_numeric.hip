@@ -20,7 +20,8 @@
 // task of its own with the LDS table and accumulators of one wave. A window
 // streams the whole row of A, its rows of B narrowed to the window's column
 // range (by binary search in B's sorted columns for long rows, by a range
-// test for short ones); the terms of every c_ij still arrive in ascending k.
+// test for short ones), 64 (entry, B position) pairs per step; the adds of a
+// step go in rounds so that every c_ij still gets its terms in ascending k.
 #include <climits>
 #include <cstdio>
 
@@ -32,7 +33,7 @@ namespace mls {
 
 constexpr int kNumDepth = 4;   // steps whose B loads are issued together
 constexpr int kNumWinCap = 1024;   // table slots of a spill window (CAP / 2 positions)
-constexpr int kWinDepth = 8;       // spill window: steps whose B loads are issued together
+constexpr int kWinDepth = 2;       // spill window: batches of 64 pairs whose B loads are issued together
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -347,18 +348,33 @@ __global__ __launch_bounds__(kWG) void k_win_scan(Batch b, Sched sc, int m)
     if (threadIdx.x == 0) ws[n] = s_carry;
 }
 
-constexpr int kWinBlock = 4;   // consecutive windows a wave takes per counter grab
+constexpr int kWinBlock = 2;   // consecutive windows a wave takes per counter grab
 
+// LDS of one spill window: table, accumulators, staged entries, their first
+// pair and the per-position lane marks of the ordered adds
+constexpr int win_bytes(int CAP, bool PACK)
+{
+    return CAP * (PACK ? 4 : 8) + (CAP / 2) * 8 + kWave * 16 + (kWave + 1) * 4 + (CAP / 2) * 4;
+}
+
+// A window's terms are flattened: the (entry, B position) pairs of a staged
+// chunk of A's row, entry-major (so in ascending k), are taken 64 at a time,
+// one per lane, with coalesced loads of B. Two lanes of a batch may hit the
+// same output, so the adds are applied in rounds: in each round the lowest
+// pending lane of every output position adds (an LDS min over lane ids
+// finds it), which keeps every c_ij's terms in ascending k.
 template <int CAP, bool PACK, bool MULTI>
 __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
 {
     constexpr int G = kWave;
     constexpr int M = CAP / 2;   // positions of C per window
-    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK), 1);
+    constexpr int NW = nw_num(win_bytes(CAP, PACK), 1);
     constexpr int TW = PACK ? CAP : 2 * CAP;
     __shared__ __attribute__((aligned(16))) uint32_t s_tab[NW * TW];
     __shared__ double s_acc[NW * M];
-    __shared__ int4 s_par[NW * G];
+    __shared__ int4 s_par[NW * G];        // staged entries: (first B position, -, a)
+    __shared__ int s_poff[NW * (G + 1)];  // first pair of each staged entry, then the total
+    __shared__ int s_own[NW * M];
 
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;
@@ -366,6 +382,8 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
     PosTab<CAP, PACK> tab{s_tab + wave * TW};
     double *acc = s_acc + wave * M;
     int4 *par = s_par + wave * G;
+    int *poff = s_poff + wave * (G + 1);
+    int *own = s_own + wave * M;
 
     const int n_bin = gp(sc.bin_count)[kBinSpill];
     const int start = bin_start(sc.bin_count, kBinSpill);
@@ -428,8 +446,8 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
             nwave_sync();
             bool bad = false;
             for (int pc = ps; pc < pe; pc += G) {
-                // stage the chunk: (q0, q1, a) of entry pc + lane, the row of B
-                // narrowed to the window's columns when it is long
+                // stage the chunk: entry pc + lane's row of B, narrowed to the
+                // window's columns when it is long, and its pair count
                 int sq0 = 0, sq1 = 0;
                 double sa = 0.0;
                 if (pc + lane < pe) {
@@ -444,41 +462,59 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
                         }
                     }
                 }
-                par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
+                const int np = sq1 > sq0 ? sq1 - sq0 : 0;
+                int incl = np;
+#pragma unroll
+                for (int o = 1; o < G; o <<= 1) {
+                    const int y = __shfl_up(incl, o, G);
+                    if (lane >= o) incl += y;
+                }
+                const int total = __shfl(incl, G - 1, G);
+                poff[lane] = incl - np;
+                if (lane == 0) poff[G] = total;
+                par[lane] = make_int4(sq0, 0, __double2loint(sa), __double2hiint(sa));
                 nwave_sync();
-                const int nst = min(G, pe - pc);
-                for (int u0s = 0; u0s < nst; u0s += kWinDepth) {
+                for (int base = 0; base < total; base += G * kWinDepth) {
+                    // kWinDepth batches of 64 pairs: loads first, then lookups,
+                    // then the ordered adds batch by batch
                     int jv[kWinDepth];
-                    double bv[kWinDepth], av[kWinDepth];
-                    uint32_t longm = 0;
+                    double tv[kWinDepth];
 #pragma unroll
                     for (int d = 0; d < kWinDepth; ++d) {
-                        jv[d] = -1; bv[d] = 0.0; av[d] = 0.0;
-                        if (u0s + d < nst) {
-                            const int4 pr = par[u0s + d];
-                            av[d] = __hiloint2double(pr.w, pr.z);
-                            if (pr.y - pr.x > G) longm |= 1u << d;
-                            const int q = pr.x + lane;
-                            if (q < pr.y) { jv[d] = bci[q]; bv[d] = bval[q]; }
+                        jv[d] = -1;
+                        tv[d] = 0.0;
+                        const int pp = base + d * G + lane;
+                        if (pp < total) {
+                            int lo = 0, hi = G - 1;   // largest e with poff[e] <= pp
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (poff[mid] <= pp) lo = mid; else hi = mid - 1;
+                            }
+                            const int4 pr = par[lo];
+                            const int q = pr.x + (pp - poff[lo]);
+                            jv[d] = bci[q];
+                            tv[d] = __hiloint2double(pr.w, pr.z) * bval[q];
                         }
                     }
                     int posv[kWinDepth];
 #pragma unroll
-                    for (int d = 0; d < kWinDepth; ++d)
+                    for (int d = 0; d < kWinDepth; ++d) {
                         posv[d] = (jv[d] >= 0 && jv[d] >= jlo && jv[d] <= jhi) ? tab.lookup(logcap, jv[d]) : -2;
+                        if (posv[d] == -1) bad = true;
+                    }
 #pragma unroll
                     for (int d = 0; d < kWinDepth; ++d) {
-                        if (posv[d] >= 0) atomicAdd(acc + posv[d], av[d] * bv[d]);
-                        else if (posv[d] == -1) bad = true;
-                        if ((longm >> d) & 1u) {
-                            const int4 pr = par[u0s + d];
-                            for (int q = pr.x + G + lane; q < pr.y; q += G) {
-                                const int j = bci[q];
-                                if (j < jlo || j > jhi) continue;
-                                const int pos = tab.lookup(logcap, j);
-                                if (pos >= 0) atomicAdd(acc + pos, av[d] * bval[q]);
-                                else bad = true;
+                        bool pend = posv[d] >= 0;
+                        while (__ballot(pend)) {
+                            if (pend) own[posv[d]] = G;
+                            nwave_sync();
+                            if (pend) atomicMin(own + posv[d], lane);
+                            nwave_sync();
+                            if (pend && own[posv[d]] == lane) {
+                                atomicAdd(acc + posv[d], tv[d]);
+                                pend = false;
                             }
+                            nwave_sync();
                         }
                     }
                 }
@@ -535,7 +571,7 @@ static void launch_num_class(const Batch &b, const Sched &sc, int bin, hipStream
 template <int CAP, bool PACK, bool MULTI>
 static void launch_num_win(const Batch &b, const Sched &sc, hipStream_t s)
 {
-    constexpr int NW = nw_num(num_row_bytes(CAP, kWave, PACK), 1);
+    constexpr int NW = nw_num(win_bytes(CAP, PACK), 1);
     static int grid = persistent_grid_n(k_num_win<CAP, PACK, MULTI>, NW * kWave);
     static char name[64];
     if (!name[0]) snprintf(name, sizeof(name), "num_spill_C%d%s%s", CAP, PACK ? "_p" : "", MULTI ? "_b" : "");
