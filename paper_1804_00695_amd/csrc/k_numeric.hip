@@ -389,6 +389,9 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
     const int start = bin_start(sc.bin_count, kBinSpill);
     const MLS_G int32_t *wst = gp(sc.wstart);
     const int nwin = n_bin > 0 ? wst[n_bin] : 0;
+    // one counter over all windows: their work varies too much (a hub row's
+    // windows are consecutive and long) for per-XCD slabs
+    if (nwin == 0) return;
     int32_t *cursor = sc.task_cursor + kBinSpill * kXcd;
     ProbCache pcache;
     for (;;) {
