@@ -8,9 +8,11 @@
 // sorted by set in LDS (bitonic network), and their bits expand into
 // ascending columns at offsets from a scan of the popcounts.
 //
-// Spill path (rows whose word bound exceeds the largest LDS class): one
-// workgroup per row with a dense bitmap over all columns in global memory;
-// scanning the bitmap in order yields sorted columns directly.
+// Spill path (rows whose word bound exceeds the largest LDS class, and large
+// rows whose dense bitmap is smaller than their class table): one workgroup
+// per row with a dense bitmap over C's columns in LDS (column windows when C
+// is wider than the LDS holds); scanning the bitmap in order yields sorted
+// columns directly.
 #include <cstdio>
 
 #include "common.h"
