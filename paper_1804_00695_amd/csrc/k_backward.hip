@@ -173,19 +173,29 @@ __device__ __forceinline__ int lower_col_w(const MLS_G int32_t *cols, int lo, in
     return lo;
 }
 
-constexpr int kBwdWinCap = 2048;   // table slots of a spill window (CAP / 2 positions of W_i)
+constexpr int kBwdWinCap = 1024;   // table slots of a spill window (CAP / 2 positions of W_i)
+constexpr int kBwdWinDepth = 2;    // batches of 64 pairs whose B loads are issued together
 constexpr int kBwdWinBlock = 4;    // consecutive windows a wave takes per counter grab
 
+// LDS of one spill window: hash keys and W values, staged entries, their
+// first pair, and the entries' dA parts
+constexpr int bwd_win_bytes(int CAP) { return CAP * 12 + kWave * 16 + (kWave + 1) * 4 + kWave * 8; }
+
 // Windows of the spill rows come from k_win_scan (same rule: ceil(nnz(W_i) / M)).
+// A window's (entry, B position) pairs are flattened, 64 per step: each pair
+// adds a_ik W_ij into dB with a device atomic and W_ij b_kj into its entry's
+// dA part in LDS; the parts go to dA with one device atomic per entry.
 template <int CAP>
 __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, double *dB)
 {
     constexpr int G = kWave;
     constexpr int M = CAP / 2;
-    constexpr int NW = nw_bwd(CAP * 12, 1);
+    constexpr int NW = nw_bwd(bwd_win_bytes(CAP), 1);
     __shared__ int s_key[NW * CAP];
     __shared__ double s_wv[NW * CAP];
-    __shared__ int4 s_par[NW * G];   // staged entries of row i of A: (q0, q1, a)
+    __shared__ int4 s_par[NW * G];        // staged entries: (first B position, -, a)
+    __shared__ int s_poff[NW * (G + 1)];  // first pair of each staged entry, then the total
+    __shared__ double s_da[NW * G];
 
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;
@@ -193,6 +203,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
     int *key = s_key + wave * CAP;
     double *wv = s_wv + wave * CAP;
     int4 *par = s_par + wave * G;
+    int *poff = s_poff + wave * (G + 1);
+    double *da = s_da + wave * G;
 
     const Prob P = b.p0;
     const MLS_G int32_t *__restrict__ arp = gp(P.arp);
@@ -269,32 +281,52 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
                         if (jhi != INT_MAX) sq1 = lower_col_w(bci, sq0, sq1, jhi + 1);
                     }
                 }
-                par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
-                bwd_sync();
-                const int nst = min(G, pe - pc);
-                for (int d0 = 0; d0 < nst; d0 += kBwdUnroll) {
-                    double part[kBwdUnroll];
+                const int np = sq1 > sq0 ? sq1 - sq0 : 0;
+                int incl = np;
 #pragma unroll
-                    for (int d = 0; d < kBwdUnroll; ++d) {
-                        part[d] = 0.0;
-                        if (d0 + d >= nst) continue;
-                        const int4 pr = par[d0 + d];
-                        const double a = __hiloint2double(pr.w, pr.z);
-                        for (int q = pr.x + lane; q < pr.y; q += G) {
-                            const int j = bci[q];
-                            if (j < jlo || j > jhi) continue;
-                            double w;
-                            if (!w_lookup(key, wv, logcap, j, w)) { bad = true; continue; }
-                            part[d] += w * bval[q];
-                            if (dB) atomicAdd(dB + q, a * w);
+                for (int o = 1; o < G; o <<= 1) {
+                    const int y = __shfl_up(incl, o, G);
+                    if (lane >= o) incl += y;
+                }
+                const int total = __shfl(incl, G - 1, G);
+                poff[lane] = incl - np;
+                if (lane == 0) poff[G] = total;
+                par[lane] = make_int4(sq0, 0, __double2loint(sa), __double2hiint(sa));
+                da[lane] = 0.0;
+                bwd_sync();
+                for (int base = 0; base < total; base += G * kBwdWinDepth) {
+                    int ev[kBwdWinDepth], qv[kBwdWinDepth], jv[kBwdWinDepth];
+                    double bv[kBwdWinDepth], av[kBwdWinDepth];
+#pragma unroll
+                    for (int d = 0; d < kBwdWinDepth; ++d) {
+                        jv[d] = -1; ev[d] = 0; qv[d] = 0; bv[d] = 0.0; av[d] = 0.0;
+                        const int pp = base + d * G + lane;
+                        if (pp < total) {
+                            int lo = 0, hi = G - 1;   // largest e with poff[e] <= pp
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (poff[mid] <= pp) lo = mid; else hi = mid - 1;
+                            }
+                            const int4 pr = par[lo];
+                            ev[d] = lo;
+                            qv[d] = pr.x + (pp - poff[lo]);
+                            av[d] = __hiloint2double(pr.w, pr.z);
+                            jv[d] = bci[qv[d]];
+                            bv[d] = bval[qv[d]];
                         }
                     }
 #pragma unroll
-                    for (int d = 0; d < kBwdUnroll; ++d) {
-                        const double sum = group_sum<G>(part[d]);
-                        if (dA && lane == 0 && d0 + d < nst && sum != 0.0) atomicAdd(dA + pc + d0 + d, sum);
+                    for (int d = 0; d < kBwdWinDepth; ++d) {
+                        const int j = jv[d];
+                        if (j < 0 || j < jlo || j > jhi) continue;
+                        double w;
+                        if (!w_lookup(key, wv, logcap, j, w)) { bad = true; continue; }
+                        if (dA) atomicAdd(da + ev[d], w * bv[d]);
+                        if (dB) atomicAdd(dB + qv[d], av[d] * w);
                     }
                 }
+                bwd_sync();
+                if (dA && pc + lane < pe && da[lane] != 0.0) atomicAdd(dA + pc + lane, da[lane]);
                 bwd_sync();
             }
             if (bad) atomicOr(sc.err, kErrStructure);
@@ -340,7 +372,7 @@ void launch_backward(const Batch &b, const Sched &sc, const double *wval, double
     else launch_bwd_class<32, kFillCap[2]>(b, sc, 2, dA, dB, s);
     launch_bwd_class<64, kFillCap[3]>(b, sc, 3, dA, dB, s);
     launch_bwd_class<64, kFillCap[4]>(b, sc, 4, dA, dB, s);
-    constexpr int NWW = nw_bwd(kBwdWinCap * 12, 1);
+    constexpr int NWW = nw_bwd(bwd_win_bytes(kBwdWinCap), 1);
     static int win_grid = bwd_grid(k_bwd_win<kBwdWinCap>, NWW * kWave);
     ProfScope ps("bwd_spill", s);
     hipLaunchKernelGGL(k_win_scan, dim3(1), dim3(kWG), 0, s, b, sc, kBwdWinCap / 2);
