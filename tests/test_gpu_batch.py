@@ -88,3 +88,28 @@ def test_galerkin_two_stages_symmetric():
     APo, _ = oracle.spgemm(A, P)
     Aco, _ = oracle.spgemm(R, APo)
     assert np.array_equal(v, Aco.values)
+
+
+def test_batch_with_spill_rows():
+    # a batch whose products include rows of C past the LDS classes (a power-
+    # law square and wide rows): the batched symbolic bitmaps and the batched
+    # numeric windows, next to small multigrid products; also as a graph plan
+    G = synth.rmat_graph(12, 8, seed=5)
+    Rm = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), 8))
+    g = synth.rng(21)
+    rows = [np.sort(g.choice(6000, 1500, replace=False)) for _ in range(6)]
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    W = synth.Csr(6, 6000, rp, np.concatenate(rows).astype(np.int32), g.standard_normal(int(rp[-1])))
+    prods = [synth.amg_instance(5)[:2], (Rm, Rm), (W, synth.poisson_csr(6000, 20000, 8.0, 22)),
+             synth.amg_instance(6)[:2]]
+    As, Bs = to_dev(prods)
+    Cs = mls.batch_symbolic(As, Bs)
+    mls.batch_numeric(As, Bs, Cs)
+    check_all(prods, Cs)
+    plan = mls.BatchPlan(As, Bs, Cs, use_graph=True)
+    for rep in range(2):
+        for C in Cs:
+            C.values.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.run()
+        check_all(prods, Cs)
