@@ -3,9 +3,10 @@
 //   dA_ik = sum_{j in B_k} W_ij b_kj      (only on the pattern of A)
 //   dB_kj = sum_{i : k in A_i} a_ik W_ij  (only on the pattern of B)
 // Fused, with no dense or product-sized intermediate: G lanes own row i;
-// W_i goes into an LDS hash (column -> W value); for every entry (i, k) the
-// lanes take distinct entries of B_k, look up W_ij, accumulate W_ij b_kj for
-// dA (group reduction) and add a_ik W_ij into dB with a device fp64 atomic.
+// W_i goes into an LDS hash (column -> W value); the pairs (entry (i, k),
+// entry of B_k) of a chunk of A_i are flattened, one per lane: each looks up
+// W_ij, adds W_ij b_kj to the entry's dA sum in LDS and a_ik W_ij into dB
+// with a device fp64 atomic.
 // Rows of W too long for LDS are cut into windows of consecutive positions of
 // W_i, each a task of one wave with its own LDS hash; a window streams the
 // row of A with its rows of B narrowed to the window's column range, and adds
@@ -52,13 +53,40 @@ __device__ __forceinline__ bool w_lookup(const int *key, const double *wv, int l
     return false;
 }
 
+// LDS of one row: W_i's hash (key, value), the staged entries of A (first B
+// position, a_ik, their dA sums) and the staged entries' first pairs
+constexpr int bwd_row_bytes(int CAP, int G) { return CAP * 12 + G * 20 + (G + 1) * 4; }
+
+// Waves per workgroup that keep the most waves resident on a CU (160 KB of
+// LDS, 32 waves), given the LDS of one wave.
+constexpr int nw_bwd_best(int wave_bytes)
+{
+    int best = 1, best_w = 0;
+    for (int nw = 1; nw <= 4; ++nw) {
+        int wgs = 163840 / (nw * wave_bytes);
+        int w = wgs * nw;
+        if (w > 32) w = 32;
+        if (65536 < nw * wave_bytes) w = 0;   // a workgroup's static LDS stays within 64 KB
+        if (w >= best_w) { best = nw; best_w = w; }
+    }
+    return best;
+}
+
+// Rows of W in LDS: G lanes own row i. The pairs (entry of A_i, position in
+// B_k) of a staged chunk of A_i are flattened and taken G at a time, one per
+// lane: W_ij is looked up, a_ik W_ij goes to dB with a device atomic and
+// W_ij b_kj to the entry's dA sum in LDS, written out once per entry.
 template <int G, int CAP>
 __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, double *dA, double *dB)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_bwd(CAP * 12, W);
+    constexpr int NW = nw_bwd_best(bwd_row_bytes(CAP, G) * W);
     __shared__ int s_key[NW * W * CAP];
     __shared__ double s_wv[NW * W * CAP];
+    __shared__ double s_pa[NW * W * G];
+    __shared__ double s_da[NW * W * G];
+    __shared__ int s_pq[NW * W * G];
+    __shared__ int s_poff[NW * W * (G + 1)];
 
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;
@@ -67,6 +95,10 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
     const int rs = wave * W + slot;
     int *key = s_key + rs * CAP;
     double *wv = s_wv + rs * CAP;
+    double *pa = s_pa + rs * G;
+    double *da = s_da + rs * G;
+    int *pq = s_pq + rs * G;
+    int *poff = s_poff + rs * (G + 1);
 
     const Prob P = b.p0;
     const MLS_G int32_t *__restrict__ arp = gp(P.arp);
@@ -114,39 +146,65 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
         }
         bwd_sync();
         bool bad = false;
-        // loop bounds are made uniform across the wave so that the group
-        // reductions (cross-lane shuffles) run with every lane present
-        int pmax = pe - ps;
-        for (int o = 32; o >= 1; o >>= 1) pmax = max(pmax, __shfl_xor(pmax, o, kWave));
-        for (int off = 0; off < pmax; off += kBwdUnroll) {
-            double av[kBwdUnroll], part[kBwdUnroll];
-            int q0[kBwdUnroll], q1[kBwdUnroll];
-#pragma unroll
-            for (int u = 0; u < kBwdUnroll; ++u) {
-                const int p = ps + off + u;
-                q0[u] = 0; q1[u] = 0; av[u] = 0.0; part[u] = 0.0;
-                if (active && p < pe) {
-                    int k = aci[p];
-                    av[u] = aval[p];
-                    q0[u] = brp[k];
-                    q1[u] = brp[k + 1];
-                }
+        // the chunk loop runs to the wave's longest row, so that the group
+        // scans (cross-lane shuffles) run with every lane present
+        int nch = (pe - ps + G - 1) / G;
+        for (int o = 32; o >= 1; o >>= 1) nch = max(nch, __shfl_xor(nch, o, kWave));
+        for (int c = 0; c < nch; ++c) {
+            const int pc = ps + c * G;
+            int q0 = 0, np = 0;
+            double a = 0.0;
+            if (pc + lane < pe) {
+                const int k = aci[pc + lane];
+                a = aval[pc + lane];
+                q0 = brp[k];
+                const int q1 = brp[k + 1];
+                np = q1 > q0 ? q1 - q0 : 0;
             }
+            int incl = np;
 #pragma unroll
-            for (int u = 0; u < kBwdUnroll; ++u) {
-                for (int q = q0[u] + lane; q < q1[u]; q += G) {
+            for (int o = 1; o < G; o <<= 1) {
+                const int y = __shfl_up(incl, o, G);
+                if (lane >= o) incl += y;
+            }
+            const int total = __shfl(incl, G - 1, G);
+            poff[lane] = incl - np;
+            if (lane == 0) poff[G] = total;
+            pq[lane] = q0;
+            pa[lane] = a;
+            da[lane] = 0.0;
+            bwd_sync();
+            for (int base = 0; base < total; base += G * kBwdUnroll) {
+                int qv[kBwdUnroll], ev[kBwdUnroll], jv[kBwdUnroll];
+                double bv[kBwdUnroll];
+#pragma unroll
+                for (int d = 0; d < kBwdUnroll; ++d) {
+                    jv[d] = -1; qv[d] = 0; ev[d] = 0; bv[d] = 0.0;
+                    const int pp = base + d * G + lane;
+                    if (pp < total) {
+                        int lo = 0, hi = G - 1;   // largest e with poff[e] <= pp
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (poff[mid] <= pp) lo = mid; else hi = mid - 1;
+                        }
+                        ev[d] = lo;
+                        qv[d] = pq[lo] + (pp - poff[lo]);
+                        jv[d] = bci[qv[d]];
+                        bv[d] = bval[qv[d]];
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < kBwdUnroll; ++d) {
+                    if (jv[d] < 0) continue;
                     double w;
-                    if (!w_lookup(key, wv, logcap, bci[q], w)) { bad = true; continue; }
-                    part[u] += w * bval[q];
-                    if (dB) atomicAdd(dB + q, av[u] * w);
+                    if (!w_lookup(key, wv, logcap, jv[d], w)) { bad = true; continue; }
+                    if (dA) atomicAdd(da + ev[d], w * bv[d]);
+                    if (dB) atomicAdd(dB + qv[d], pa[ev[d]] * w);
                 }
             }
-#pragma unroll
-            for (int u = 0; u < kBwdUnroll; ++u) {
-                double s = group_sum<G>(part[u]);
-                const int p = ps + off + u;
-                if (dA && active && lane == 0 && p < pe) gdA[p] = s;
-            }
+            bwd_sync();
+            if (dA && pc + lane < pe) gdA[pc + lane] = da[lane];
+            bwd_sync();
         }
         if (bad) atomicOr(sc.err, kErrStructure);
         bwd_sync();
@@ -348,7 +406,7 @@ template <int G, int CAP>
 static void launch_bwd_class(const Batch &b, const Sched &sc, int bin, double *dA, double *dB, hipStream_t s)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_bwd(CAP * 12, W);
+    constexpr int NW = nw_bwd_best(bwd_row_bytes(CAP, G) * W);
     static int grid = bwd_grid(k_bwd_lds<G, CAP>, NW * kWave);
     static char name[64];
     if (!name[0]) snprintf(name, sizeof(name), "bwd_lds_G%d_C%d", G, CAP);
