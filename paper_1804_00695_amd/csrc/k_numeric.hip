@@ -33,7 +33,9 @@ namespace mls {
 
 constexpr int kNumDepth = 4;   // steps whose B loads are issued together
 constexpr int kNumWinCap = 1024;   // table slots of a spill window (CAP / 2 positions)
-constexpr int kWinDepth = 2;       // spill window: batches of 64 pairs whose B loads are issued together
+constexpr int kWinDepth = 2;
+constexpr bool kNumFlat = true;    // flattened pairs for the classes of at most kNumFlatMaxG lanes per row
+constexpr int kNumFlatMaxG = 8;       // spill window: batches of 64 pairs whose B loads are issued together
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -166,13 +168,21 @@ __device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, boo
     return m;
 }
 
-template <int G, int CAP, bool PACK, bool MULTI>
+// FLAT: the (entry, B position) pairs of a staged chunk are flattened, G at a
+// time, one per lane (for rows of B shorter than G, which would leave lanes
+// idle); the adds of a step go in rounds in which the lowest pending lane of
+// every output position adds, so the terms still arrive in ascending k. Its
+// lane marks and the staged pair offsets follow the tables in LDS.
+constexpr int num_flat_words(int CAP, int G) { return CAP / 2 + G + 1; }
+
+template <int G, int CAP, bool PACK, bool MULTI, bool FLAT>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 : 8))) void k_num_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK), W);
+    constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
+    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
     constexpr int TW = PACK ? CAP : 2 * CAP;   // table words per row
-    __shared__ __attribute__((aligned(16))) uint32_t s_tab[NW * W * TW];
+    __shared__ __attribute__((aligned(16))) uint32_t s_tab[NW * W * (TW + XW)];
     __shared__ double s_acc[NW * W * (CAP / 2)];
     __shared__ int4 s_par[NW * W * G];   // staged entries of row i of A: (q0, q1, a)
 
@@ -184,6 +194,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
     PosTab<CAP, PACK> tab{s_tab + rs * TW};
     double *acc = s_acc + rs * (CAP / 2);
     int4 *par = s_par + rs * G;
+    int *own = (int *)(s_tab + NW * W * TW) + rs * XW;   // FLAT only: lane marks, then pair offsets
+    int *poff = own + CAP / 2;
 
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
@@ -241,12 +253,68 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
                 sq1 = brp[ka - k_lo + 1] - b_off;
             }
             par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
+            int total = 0;
+            if constexpr (FLAT) {
+                const int np = sq1 > sq0 ? sq1 - sq0 : 0;
+                int incl = np;
+#pragma unroll
+                for (int o = 1; o < G; o <<= 1) {
+                    const int y = __shfl_up(incl, o, G);
+                    if (lane >= o) incl += y;
+                }
+                total = __shfl(incl, G - 1, G);
+                poff[lane] = incl - np;
+            }
             nwave_sync();
             // the next chunk's entries of A are in flight during this chunk's steps
             ka = -1;
             sa = 0.0;
             if (pc + G + lane < pe) { ka = aci[pc + G + lane]; sa = aval[pc + G + lane]; }
-            const int n = min(G, pe - pc);
+            const int n = FLAT ? 0 : min(G, pe - pc);
+            if constexpr (FLAT) {
+                for (int base = 0; base < total; base += G * kNumDepth) {
+                    int jv[kNumDepth];
+                    double tv[kNumDepth];
+#pragma unroll
+                    for (int d = 0; d < kNumDepth; ++d) {
+                        jv[d] = -1;
+                        tv[d] = 0.0;
+                        const int pp = base + d * G + lane;
+                        if (pp < total) {
+                            int lo = 0, hi = G - 1;   // largest e with poff[e] <= pp
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (poff[mid] <= pp) lo = mid; else hi = mid - 1;
+                            }
+                            const int4 pr = par[lo];
+                            const int q = pr.x + (pp - poff[lo]);
+                            jv[d] = bci[q];
+                            tv[d] = __hiloint2double(pr.w, pr.z) * bval[q];
+                        }
+                    }
+                    int posv[kNumDepth];
+#pragma unroll
+                    for (int d = 0; d < kNumDepth; ++d) {
+                        posv[d] = jv[d] >= 0 ? tab.lookup(logcap, jv[d]) : -2;
+                        if (posv[d] == -1) bad = true;
+                    }
+#pragma unroll
+                    for (int d = 0; d < kNumDepth; ++d) {
+                        bool pend = posv[d] >= 0;
+                        while (__ballot(pend)) {
+                            if (pend) own[posv[d]] = G;
+                            nwave_sync();
+                            if (pend) atomicMin(own + posv[d], lane);
+                            nwave_sync();
+                            if (pend && own[posv[d]] == lane) {
+                                atomicAdd(acc + posv[d], tv[d]);
+                                pend = false;
+                            }
+                            nwave_sync();
+                        }
+                    }
+                }
+            }
             for (int u0 = 0; u0 < n; u0 += kNumDepth) {
                 // issue the B loads of kNumDepth steps, then accumulate them in order
                 int jv[kNumDepth];
@@ -545,13 +613,16 @@ static int persistent_grid_n(K kernel, int threads)
 template <int G, int CAP, bool PACK, bool MULTI>
 static void launch_num_variant(const Batch &b, const Sched &sc, int bin, hipStream_t s)
 {
+    constexpr bool FLAT = kNumFlat && G <= kNumFlatMaxG;
     constexpr int W = kWave / G;
-    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK), W);
-    static int grid = persistent_grid_n(k_num_lds<G, CAP, PACK, MULTI>, NW * kWave);
+    constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
+    constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
+    static int grid = persistent_grid_n(k_num_lds<G, CAP, PACK, MULTI, FLAT>, NW * kWave);
     static char name[64];
-    if (!name[0]) snprintf(name, sizeof(name), "num_lds_G%d_C%d%s%s", G, CAP, PACK ? "_p" : "", MULTI ? "_b" : "");
+    if (!name[0])
+        snprintf(name, sizeof(name), "num_lds_G%d_C%d%s%s%s", G, CAP, PACK ? "_p" : "", MULTI ? "_b" : "", FLAT ? "_f" : "");
     ProfScope ps(name, s);
-    hipLaunchKernelGGL((k_num_lds<G, CAP, PACK, MULTI>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
+    hipLaunchKernelGGL((k_num_lds<G, CAP, PACK, MULTI, FLAT>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
 }
 
 template <int G, int CAP, bool PACK>
