@@ -398,44 +398,70 @@ def _handles(mats):
     return arr
 
 
-def batch_workspace_size(As, Bs) -> int:
+def batch_workspace_size(As, Bs, ha=None, hb=None) -> int:
     n = ctypes.c_size_t(0)
-    check(lib.spgemm_batch_workspace_size(len(As), _handles(As), _handles(Bs), ctypes.byref(n)),
+    check(lib.spgemm_batch_workspace_size(len(As), _handles(As) if ha is None else ha,
+                                          _handles(Bs) if hb is None else hb, ctypes.byref(n)),
           "spgemm_batch_workspace_size")
     return n.value
 
 
+def _pooled(sizes, dtype, dev, align=64):
+    """One allocation holding arrays of the given sizes, each starting at a
+    multiple of `align` elements: (buffer, element offsets, exact-size views)."""
+    padded = [(z + align - 1) // align * align for z in sizes]
+    offs = np.concatenate([[0], np.cumsum(padded)]).astype(np.int64)
+    buf = torch.empty(max(int(offs[-1]), 1), dtype=dtype, device=dev)
+    parts = []
+    for z, pz in zip(sizes, padded):
+        parts += [z, pz - z]
+    tail = buf.numel() - int(offs[-1])
+    views = torch.split(buf, parts + ([tail] if tail else []))[0:2 * len(sizes):2]
+    return buf, offs, views
+
+
 def batch_symbolic(As, Bs, ws: Optional[Workspace] = None, with_values: bool = True):
-    """Structures of all C_t = A_t * B_t: one count pass (one readback), one fill pass."""
+    """Structures of all C_t = A_t * B_t: one count pass (one readback), one fill pass.
+    The outputs' arrays are views into one allocation per array kind."""
     dev = As[0].row_ptr.device
     w = _ws(ws, dev)
-    nb = batch_workspace_size(As, Bs)
-    p = w.get(nb)
-    Cs = [DeviceCsr(a.nrows, b.ncols, torch.empty(a.nrows + 1, dtype=torch.int32, device=dev),
-                    torch.empty(0, dtype=torch.int32, device=dev), None) for a, b in zip(As, Bs)]
-    nnz = (ctypes.c_int64 * len(As))()
     ha, hb = _handles(As), _handles(Bs)
-    check(lib.spgemm_batch_symbolic(len(As), ha, hb, _handles(Cs), 0, nnz, p, nb, stream_handle()),
+    nb = batch_workspace_size(As, Bs, ha, hb)
+    p = w.get(nb)
+    nt = len(As)
+    rp_buf, rp_off, rps = _pooled([a.nrows + 1 for a in As], torch.int32, dev)
+    rp0 = rp_buf.data_ptr()
+    hc = (CsrT * nt)()
+    for t in range(nt):
+        q = rp0 + 4 * int(rp_off[t])
+        hc[t] = CsrT(As[t].nrows, Bs[t].ncols, 0, q, q, None)
+    nnz = (ctypes.c_int64 * nt)()
+    check(lib.spgemm_batch_symbolic(nt, ha, hb, hc, 0, nnz, p, nb, stream_handle()),
           "spgemm_batch_symbolic(count)")
-    for c, z in zip(Cs, nnz):
-        c.col_idx = torch.empty(int(z), dtype=torch.int32, device=dev)
-        if with_values:
-            c.values = torch.empty(int(z), dtype=torch.float64, device=dev)
-    hc = _handles(Cs)
-    for i, c in enumerate(Cs):   # handles must carry col_idx even when nnz == 0
-        if c.nnz == 0:
-            hc[i].col_idx = c.row_ptr.data_ptr()
-    check(lib.spgemm_batch_symbolic(len(As), ha, hb, hc, 1, None, p, nb, stream_handle()),
+    zs = [int(z) for z in nnz]
+    ci_buf, ci_off, cis = _pooled(zs, torch.int32, dev)
+    vs = [None] * nt
+    v0 = 0
+    if with_values:
+        v_buf, _, vs = _pooled(zs, torch.float64, dev)
+        v0 = v_buf.data_ptr()
+    c0 = ci_buf.data_ptr()
+    for t in range(nt):
+        hc[t].nnz = zs[t]
+        hc[t].col_idx = c0 + 4 * int(ci_off[t])
+        hc[t].values = (v0 + 8 * int(ci_off[t])) if with_values else None
+    check(lib.spgemm_batch_symbolic(nt, ha, hb, hc, 1, None, p, nb, stream_handle()),
           "spgemm_batch_symbolic(fill)")
-    return Cs
+    return [DeviceCsr(a.nrows, b.ncols, rps[t], cis[t], vs[t]) for t, (a, b) in enumerate(zip(As, Bs))]
 
 
 def batch_numeric(As, Bs, Cs, ws: Optional[Workspace] = None):
     dev = As[0].row_ptr.device
     w = _ws(ws, dev)
-    nb = batch_workspace_size(As, Bs)
-    check(lib.spgemm_batch_numeric(len(As), _handles(As), _handles(Bs), _handles(Cs), w.get(nb), nb,
-                                   stream_handle()), "spgemm_batch_numeric")
+    ha, hb = _handles(As), _handles(Bs)
+    nb = batch_workspace_size(As, Bs, ha, hb)
+    check(lib.spgemm_batch_numeric(len(As), ha, hb, _handles(Cs), w.get(nb), nb, stream_handle()),
+          "spgemm_batch_numeric")
     return Cs
 
 
