@@ -251,7 +251,7 @@ __device__ __forceinline__ int class_of(int mode, int64_t size, int force_spill)
     return kBinSpill;
 }
 
-constexpr int kBinRG = 8;                    // lanes per row where the size is gathered
+constexpr int kBinRG = 4;                    // lanes per row where the size is gathered (measured: 2-16)
 constexpr int kBinSlots = kWG / kBinRG;      // rows in flight per workgroup
 constexpr int kBinLongRow = 512;             // rows of A longer than this are gathered by the workgroup
 constexpr int kBinMaxLong = 64;              // such rows deferred per block (more are gathered in place)
