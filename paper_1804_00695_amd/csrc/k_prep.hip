@@ -105,10 +105,11 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
 
 // Column compression of every B row (set = col >> 5, mask bit = col & 31),
 // padded layout: the words of row k start at B's entry offset of row k.
-// One thread per row walks rows of up to kCompressShort entries; the wave
-// takes longer rows together, 64 entries per step: a lane starts a word where its
-// set differs from the previous entry's, masks are OR-ed in LDS, and the last
-// word of a step stays open (it may continue in the next step).
+// One thread per row walks rows of up to kCompressShort entries; rows of up to
+// 32 entries take half a wave each, two at a time; the wave takes longer rows
+// together, 64 entries per step: a lane starts a word where its set differs
+// from the previous entry's, masks are OR-ed in LDS, and the last word of a
+// step stays open (it may continue in the next step).
 constexpr int kCompressShort = 16;   // longest row a single thread compresses (measured)
 
 __global__ __launch_bounds__(kWG) void k_compress(Batch b)
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
     uint32_t *wmsk = s_msk[wave];
     const uint32_t kNone = 0xffffffffu;
     const int g = blockIdx.x * kWG + threadIdx.x;
-    bool longrow = false;
+    bool longrow = false, midrow = false;
     const int32_t *ci_row = nullptr;
     uint2 *out_row = nullptr;
     int32_t *cnt_ptr = nullptr;
@@ -157,9 +158,63 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
             }
             if (cur != kNone) { u32x2 w; w.x = cur; w.y = msk; out[nout++] = w; }
             gpw(cnt_ptr)[0] = nout;
+        } else if (len <= kWave / 2) {
+            midrow = true;
         } else {
             longrow = true;
         }
+    }
+    // rows of kCompressShort + 1 .. 32 entries: two at a time, one per half wave
+    unsigned long long mm = __ballot(midrow);
+    const int half = lane >> 5, hl = lane & 31;
+    while (mm) {
+        int pick = -1;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int r = mm ? __ffsll((long long)mm) - 1 : -1;
+            if (mm) mm &= mm - 1ull;
+            if (j == half) pick = r;
+        }
+        // every lane takes part in the shuffles (a half without a row reads lane 0)
+        const int from = pick >= 0 ? pick : 0;
+        int n = __shfl(len, from, kWave);
+        if (pick < 0) n = 0;
+        const uint64_t pc_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)ci_row >> 32), from, kWave) << 32) |
+                             (uint32_t)__shfl((int)(uint64_t)ci_row, from, kWave);
+        const uint64_t po_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)out_row >> 32), from, kWave) << 32) |
+                             (uint32_t)__shfl((int)(uint64_t)out_row, from, kWave);
+        const uint64_t pn_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)cnt_ptr >> 32), from, kWave) << 32) |
+                             (uint32_t)__shfl((int)(uint64_t)cnt_ptr, from, kWave);
+        const bool valid = hl < n;
+        const uint32_t cv = valid ? (uint32_t)((const MLS_G int32_t *)pc_)[hl] : 0u;
+        const uint32_t set = valid ? (cv >> 5) : kNone;
+        uint32_t prev = __shfl_up(set, 1, kWave / 2);
+        if (hl == 0) prev = kNone;
+        const bool head = valid && set != prev;
+        const uint32_t hm = (uint32_t)(__ballot(head) >> (32 * half));
+        const int lw = __popc(hm & ((2u << hl) - 1u)) - 1;   // word of this entry (entry 0 is a head)
+        uint32_t *hs = wset + 32 * half;
+        uint32_t *hk = wmsk + 32 * half;
+        hk[hl] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (valid) {
+            atomicOr(&hk[lw], 1u << (cv & 31u));
+            if (head) hs[lw] = set;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const int nh = __popc(hm);
+        if (hl < nh) {
+            u32x2 w; w.x = hs[hl]; w.y = hk[hl];
+            ((MLS_G u32x2 *)po_)[hl] = w;
+        }
+        if (pick >= 0 && hl == 0) gpw((int32_t *)pn_)[0] = nh;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     unsigned long long lm = __ballot(longrow);
     while (lm) {
