@@ -30,7 +30,8 @@ __global__ void k_fill_f64(double *p, double v, int64_t n)
 // CSR checks over the A rows (which = 0) or B rows (which = 1) of a batch:
 // row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, columns in range and
 // strictly increasing. Column indices outside [0, nnz) are never read.
-// One thread per row walks rows of up to kShortRow entries; the wave checks
+// One thread per row walks rows of up to kShortRow entries; rows of up to 32
+// entries are checked by half a wave each, two at a time; the wave checks
 // longer rows together, one at a time, 64 entries per step.
 constexpr int kShortRow = 16;
 
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
     const int lane = threadIdx.x & 63;
     const int total = which == 0 ? b.na : b.nb;
     const int g = blockIdx.x * kWG + threadIdx.x;
-    bool bad = false, longrow = false;
+    bool bad = false, longrow = false, midrow = false;
     const int32_t *ci_row = nullptr;   // entries of this thread's row (long rows)
     int len = 0, ncols = 0;
     if (g < total) {
@@ -73,10 +74,40 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
                     bad |= cq <= prev || cq < 0 || cq >= ncols;
                     prev = cq;
                 }
+            } else if (len <= kWave / 2) {
+                midrow = true;
             } else {
                 longrow = true;
             }
         }
+    }
+    // rows of kShortRow + 1 .. 32 entries: two at a time, one per half wave
+    unsigned long long mm = __ballot(midrow);
+    const int half = lane >> 5, hl = lane & 31;
+    while (mm) {
+        int pick = -1;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int r = mm ? __ffsll((long long)mm) - 1 : -1;
+            if (mm) mm &= mm - 1ull;
+            if (j == half) pick = r;
+        }
+        // every lane takes part in the shuffles (a half without a row reads lane 0)
+        const int from = pick >= 0 ? pick : 0;
+        int n = __shfl(len, from, kWave);
+        if (pick < 0) n = 0;
+        const int nc = __shfl(ncols, from, kWave);
+        const uint64_t pa = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)ci_row >> 32), from, kWave) << 32) |
+                            (uint32_t)__shfl((int)(uint64_t)ci_row, from, kWave);
+        const bool valid = hl < n;
+        const int cq = valid ? ((const MLS_G int32_t *)pa)[hl] : 0;
+        int prev = __shfl_up(cq, 1, kWave / 2);
+        if (hl == 0) prev = -1;
+        const bool bl = valid && (cq < 0 || cq >= nc || cq <= prev);
+        // a row's verdict goes to the lane that owns it (the pick of its half)
+        const unsigned long long bb = __ballot(bl);
+        const int p0 = __shfl(pick, 0, kWave), p1 = __shfl(pick, 32, kWave);
+        if (((uint32_t)bb && lane == p0) || ((uint32_t)(bb >> 32) && lane == p1)) bad = true;
     }
     unsigned long long lm = __ballot(longrow);
     while (lm) {

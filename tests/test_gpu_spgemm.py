@@ -367,3 +367,31 @@ def test_many_long_rows_in_one_block():
     per_entry = np.diff(B.row_ptr)[A.col_idx]
     ref = np.add.reduceat(per_entry, A.row_ptr[:-1]).astype(np.int64)
     assert np.array_equal(w.cpu().numpy(), ref) and madds == int(ref.sum())
+
+
+@pytest.mark.parametrize("side", ["A", "B"])
+@pytest.mark.parametrize("length", [17, 32, 33])
+@pytest.mark.parametrize("row", [16, 17])
+@pytest.mark.parametrize("where", ["first", "last"])
+def test_device_validation_half_wave_rows(side, length, row, where):
+    # rows of 17-32 entries are checked and compressed two at a time, one per
+    # half wave (rows 16 and 17 share a step); a 33-entry row takes the wave
+    M = wide_rows(40, 500, length, 9)
+    # the compressed words of these rows first, against the oracle
+    if side == "B":
+        words, count = mls.compress(mls.DeviceCsr.from_host(M))
+        crp, sets, masks = oracle.compress(M)
+        assert np.array_equal(count.cpu().numpy(), np.diff(crp))
+    rp, ci = M.row_ptr.copy(), M.col_idx.copy()
+    s = int(rp[row])
+    if where == "first":
+        ci[s] = ci[s + 1]                        # duplicate at the row's start
+    else:
+        ci[s + length - 1] = 500                 # out of range at its end
+    Mbad = synth.Csr(M.nrows, M.ncols, rp, ci, M.values)
+    if side == "A":
+        X, Y = Mbad, synth.poisson_csr(500, 30, 4.0, 1)
+    else:
+        X, Y = synth.poisson_csr(30, 40, 4.0, 2), Mbad
+    with pytest.raises(mls.SpgemmError, match="BAD_CSR"):
+        mls.symbolic(mls.DeviceCsr.from_host(X), mls.DeviceCsr.from_host(Y))
