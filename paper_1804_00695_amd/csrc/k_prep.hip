@@ -30,10 +30,48 @@ __global__ void k_fill_f64(double *p, double v, int64_t n)
 // CSR checks over the A rows (which = 0) or B rows (which = 1) of a batch:
 // row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, columns in range and
 // strictly increasing. Column indices outside [0, nnz) are never read.
-// One thread per row walks rows of up to kShortRow entries; rows of up to 32
-// entries are checked by half a wave each, two at a time; the wave checks
-// longer rows together, one at a time, 64 entries per step.
-constexpr int kShortRow = 16;
+// One thread per row walks rows of up to kShortRow entries; rows of up to 16
+// (32) entries are checked by 16 (32) lanes each, four (two) at a time; the
+// wave checks longer rows together, one at a time, 64 entries per step.
+constexpr int kShortRow = 4;
+
+// 64 / GL rows per step, GL lanes per row (rows of at most GL entries); mm
+// holds the lanes that own such rows. A row's verdict goes to its owner lane.
+template <int GL>
+__device__ __forceinline__ void validate_group_rows(unsigned long long mm, int lane, int len, int ncols,
+                                                    const int32_t *ci_row, bool &bad)
+{
+    constexpr int NG = kWave / GL;
+    constexpr uint32_t kAll = GL == 32 ? 0xffffffffu : ((1u << GL) - 1u);
+    const int grp = lane / GL, gl = lane % GL;
+    while (mm) {
+        int pick = -1;
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            const int r = mm ? __ffsll((long long)mm) - 1 : -1;
+            if (mm) mm &= mm - 1ull;
+            if (j == grp) pick = r;
+        }
+        // every lane takes part in the shuffles (a group without a row reads lane 0)
+        const int from = pick >= 0 ? pick : 0;
+        int n = __shfl(len, from, kWave);
+        if (pick < 0) n = 0;
+        const int nc = __shfl(ncols, from, kWave);
+        const uint64_t pa = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)ci_row >> 32), from, kWave) << 32) |
+                            (uint32_t)__shfl((int)(uint64_t)ci_row, from, kWave);
+        const bool valid = gl < n;
+        const int cq = valid ? ((const MLS_G int32_t *)pa)[gl] : 0;
+        int prev = __shfl_up(cq, 1, GL);
+        if (gl == 0) prev = -1;
+        const bool bl = valid && (cq < 0 || cq >= nc || cq <= prev);
+        const unsigned long long bb = __ballot(bl);
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            const int pj = __shfl(pick, j * GL, kWave);
+            if (((uint32_t)(bb >> (j * GL)) & kAll) && lane == pj) bad = true;
+        }
+    }
+}
 
 __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int64_t *nnz_tab, uint32_t *err)
 {
@@ -81,34 +119,10 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
             }
         }
     }
-    // rows of kShortRow + 1 .. 32 entries: two at a time, one per half wave
-    unsigned long long mm = __ballot(midrow);
-    const int half = lane >> 5, hl = lane & 31;
-    while (mm) {
-        int pick = -1;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int r = mm ? __ffsll((long long)mm) - 1 : -1;
-            if (mm) mm &= mm - 1ull;
-            if (j == half) pick = r;
-        }
-        // every lane takes part in the shuffles (a half without a row reads lane 0)
-        const int from = pick >= 0 ? pick : 0;
-        int n = __shfl(len, from, kWave);
-        if (pick < 0) n = 0;
-        const int nc = __shfl(ncols, from, kWave);
-        const uint64_t pa = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)ci_row >> 32), from, kWave) << 32) |
-                            (uint32_t)__shfl((int)(uint64_t)ci_row, from, kWave);
-        const bool valid = hl < n;
-        const int cq = valid ? ((const MLS_G int32_t *)pa)[hl] : 0;
-        int prev = __shfl_up(cq, 1, kWave / 2);
-        if (hl == 0) prev = -1;
-        const bool bl = valid && (cq < 0 || cq >= nc || cq <= prev);
-        // a row's verdict goes to the lane that owns it (the pick of its half)
-        const unsigned long long bb = __ballot(bl);
-        const int p0 = __shfl(pick, 0, kWave), p1 = __shfl(pick, 32, kWave);
-        if (((uint32_t)bb && lane == p0) || ((uint32_t)(bb >> 32) && lane == p1)) bad = true;
-    }
+    // rows of kShortRow + 1 .. 16 entries four per step (16 lanes each), of
+    // 17 .. 32 entries two per step (32 lanes each)
+    validate_group_rows<16>(__ballot(midrow && len <= 16), lane, len, ncols, ci_row, bad);
+    validate_group_rows<32>(__ballot(midrow && len > 16), lane, len, ncols, ci_row, bad);
     unsigned long long lm = __ballot(longrow);
     while (lm) {
         const int src = __ffsll((long long)lm) - 1;
@@ -137,11 +151,72 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
 // Column compression of every B row (set = col >> 5, mask bit = col & 31),
 // padded layout: the words of row k start at B's entry offset of row k.
 // One thread per row walks rows of up to kCompressShort entries; rows of up to
-// 32 entries take half a wave each, two at a time; the wave takes longer rows
-// together, 64 entries per step: a lane starts a word where its set differs
+// 16 (32) entries take 16 (32) lanes each, four (two) at a time; the wave takes
+// longer rows together, 64 entries per step: a lane starts a word where its set differs
 // from the previous entry's, masks are OR-ed in LDS, and the last word of a
 // step stays open (it may continue in the next step).
-constexpr int kCompressShort = 16;   // longest row a single thread compresses (measured)
+constexpr int kCompressShort = 4;   // longest row a single thread compresses
+
+// 64 / GL rows per step, GL lanes per row (rows of at most GL entries); mm
+// holds the lanes that own such rows; wset / wmsk: the wave's 64 LDS slots.
+template <int GL>
+__device__ __forceinline__ void compress_group_rows(unsigned long long mm, int lane, int len, const int32_t *ci_row,
+                                                    uint2 *out_row, int32_t *cnt_ptr, uint32_t *wset, uint32_t *wmsk)
+{
+    constexpr int NG = kWave / GL;
+    constexpr uint32_t kAll = GL == 32 ? 0xffffffffu : ((1u << GL) - 1u);
+    constexpr uint32_t kNone = 0xffffffffu;
+    const int grp = lane / GL, gl = lane % GL;
+    while (mm) {
+        int pick = -1;
+#pragma unroll
+        for (int j = 0; j < NG; ++j) {
+            const int r = mm ? __ffsll((long long)mm) - 1 : -1;
+            if (mm) mm &= mm - 1ull;
+            if (j == grp) pick = r;
+        }
+        // every lane takes part in the shuffles (a group without a row reads lane 0)
+        const int from = pick >= 0 ? pick : 0;
+        int n = __shfl(len, from, kWave);
+        if (pick < 0) n = 0;
+        const uint64_t pc_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)ci_row >> 32), from, kWave) << 32) |
+                             (uint32_t)__shfl((int)(uint64_t)ci_row, from, kWave);
+        const uint64_t po_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)out_row >> 32), from, kWave) << 32) |
+                             (uint32_t)__shfl((int)(uint64_t)out_row, from, kWave);
+        const uint64_t pn_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)cnt_ptr >> 32), from, kWave) << 32) |
+                             (uint32_t)__shfl((int)(uint64_t)cnt_ptr, from, kWave);
+        const bool valid = gl < n;
+        const uint32_t cv = valid ? (uint32_t)((const MLS_G int32_t *)pc_)[gl] : 0u;
+        const uint32_t set = valid ? (cv >> 5) : kNone;
+        uint32_t prev = __shfl_up(set, 1, GL);
+        if (gl == 0) prev = kNone;
+        const bool head = valid && set != prev;
+        const uint32_t hm = (uint32_t)(__ballot(head) >> (GL * grp)) & kAll;
+        const int lw = __popc(hm & ((2u << gl) - 1u)) - 1;   // word of this entry (entry 0 is a head)
+        uint32_t *hs = wset + GL * grp;
+        uint32_t *hk = wmsk + GL * grp;
+        hk[gl] = 0u;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (valid) {
+            atomicOr(&hk[lw], 1u << (cv & 31u));
+            if (head) hs[lw] = set;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        const int nh = __popc(hm);
+        if (gl < nh) {
+            u32x2 w; w.x = hs[gl]; w.y = hk[gl];
+            ((MLS_G u32x2 *)po_)[gl] = w;
+        }
+        if (pick >= 0 && gl == 0) gpw((int32_t *)pn_)[0] = nh;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
 
 __global__ __launch_bounds__(kWG) void k_compress(Batch b)
 {
@@ -195,58 +270,10 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
             longrow = true;
         }
     }
-    // rows of kCompressShort + 1 .. 32 entries: two at a time, one per half wave
-    unsigned long long mm = __ballot(midrow);
-    const int half = lane >> 5, hl = lane & 31;
-    while (mm) {
-        int pick = -1;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int r = mm ? __ffsll((long long)mm) - 1 : -1;
-            if (mm) mm &= mm - 1ull;
-            if (j == half) pick = r;
-        }
-        // every lane takes part in the shuffles (a half without a row reads lane 0)
-        const int from = pick >= 0 ? pick : 0;
-        int n = __shfl(len, from, kWave);
-        if (pick < 0) n = 0;
-        const uint64_t pc_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)ci_row >> 32), from, kWave) << 32) |
-                             (uint32_t)__shfl((int)(uint64_t)ci_row, from, kWave);
-        const uint64_t po_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)out_row >> 32), from, kWave) << 32) |
-                             (uint32_t)__shfl((int)(uint64_t)out_row, from, kWave);
-        const uint64_t pn_ = ((uint64_t)(uint32_t)__shfl((int)((uint64_t)cnt_ptr >> 32), from, kWave) << 32) |
-                             (uint32_t)__shfl((int)(uint64_t)cnt_ptr, from, kWave);
-        const bool valid = hl < n;
-        const uint32_t cv = valid ? (uint32_t)((const MLS_G int32_t *)pc_)[hl] : 0u;
-        const uint32_t set = valid ? (cv >> 5) : kNone;
-        uint32_t prev = __shfl_up(set, 1, kWave / 2);
-        if (hl == 0) prev = kNone;
-        const bool head = valid && set != prev;
-        const uint32_t hm = (uint32_t)(__ballot(head) >> (32 * half));
-        const int lw = __popc(hm & ((2u << hl) - 1u)) - 1;   // word of this entry (entry 0 is a head)
-        uint32_t *hs = wset + 32 * half;
-        uint32_t *hk = wmsk + 32 * half;
-        hk[hl] = 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (valid) {
-            atomicOr(&hk[lw], 1u << (cv & 31u));
-            if (head) hs[lw] = set;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        const int nh = __popc(hm);
-        if (hl < nh) {
-            u32x2 w; w.x = hs[hl]; w.y = hk[hl];
-            ((MLS_G u32x2 *)po_)[hl] = w;
-        }
-        if (pick >= 0 && hl == 0) gpw((int32_t *)pn_)[0] = nh;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
+    // rows of kCompressShort + 1 .. 16 entries four per step (16 lanes each),
+    // of 17 .. 32 entries two per step (32 lanes each)
+    compress_group_rows<16>(__ballot(midrow && len <= 16), lane, len, ci_row, out_row, cnt_ptr, wset, wmsk);
+    compress_group_rows<32>(__ballot(midrow && len > 16), lane, len, ci_row, out_row, cnt_ptr, wset, wmsk);
     unsigned long long lm = __ballot(longrow);
     while (lm) {
         const int src = __ffsll((long long)lm) - 1;

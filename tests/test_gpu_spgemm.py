@@ -370,12 +370,13 @@ def test_many_long_rows_in_one_block():
 
 
 @pytest.mark.parametrize("side", ["A", "B"])
-@pytest.mark.parametrize("length", [17, 32, 33])
-@pytest.mark.parametrize("row", [16, 17])
+@pytest.mark.parametrize("length", [5, 16, 17, 32, 33])
+@pytest.mark.parametrize("row", [16, 17, 19])
 @pytest.mark.parametrize("where", ["first", "last"])
-def test_device_validation_half_wave_rows(side, length, row, where):
-    # rows of 17-32 entries are checked and compressed two at a time, one per
-    # half wave (rows 16 and 17 share a step); a 33-entry row takes the wave
+def test_device_validation_group_rows(side, length, row, where):
+    # rows of 5-16 (17-32) entries are checked and compressed four (two) at a
+    # time, 16 (32) lanes each, so rows 16-19 (16-17) share a step; a 33-entry
+    # row takes the wave
     M = wide_rows(40, 500, length, 9)
     # the compressed words of these rows first, against the oracle
     if side == "B":
