@@ -492,6 +492,7 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
 // words (scnt < 0) are left to the recomputing fill kernels.
 static_assert(kScratchWords == kWave, "one scratch word per lane");
 constexpr int kExpandSmall = 16;   // rows with at most this many words take the 16-lane kernel
+constexpr int kExpandMid = 32;     // rows with at most this many words take the 32-lane kernel
 
 struct ExpandRow {
     int cs, ce, t;
@@ -518,7 +519,7 @@ __device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc
     return r;
 }
 
-// Rows of more than kExpandSmall words: a wave reads the word counts of 64
+// Rows of more than kExpandMid words: a wave reads the word counts of 64
 // consecutive rows, then takes the large ones one at a time; the next large
 // row's words are loaded while the current one is ranked and written.
 __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
@@ -531,7 +532,7 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
     for (int base = w0 * kWave; base < b.na; base += nw * kWave) {
         const int gl = base + lane;
         const int nl = gl < b.na ? scnt[gl] : 0;
-        unsigned long long big = __ballot(nl > kExpandSmall);
+        unsigned long long big = __ballot(nl > kExpandMid);
         if (!big) continue;
         int r = __ffsll((long long)big) - 1;
         big &= big - 1ull;
@@ -581,13 +582,13 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
     }
 }
 
-// Rows of at most kExpandSmall words: a wave reads the word counts of 64
-// consecutive rows and takes the small non-empty ones four at a time, 16
-// lanes per row; word f of a row is read from lane f of its group by a lane
-// shuffle.
+// Rows of (NLO, G] words, G at most kExpandMid: a wave reads the word counts
+// of 64 consecutive rows and takes those rows 64 / G at a time, G lanes per
+// row; word f of a row is read from lane f of its group by a lane shuffle.
+template <int G, int NLO>
 __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
 {
-    constexpr int G = kExpandSmall;
+    static_assert(G <= kExpandMid && NLO < G, "row sizes (NLO, G] of at most kExpandMid words");
     const int lane64 = threadIdx.x & 63;
     const int slot = lane64 / G, lane = lane64 % G;
     const int nw = (int)gridDim.x * (kWG / kWave);
@@ -598,9 +599,9 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
     for (int base = w0 * kWave; base < b.na; base += nw * kWave) {
         const int gl = base + lane64;
         const int nl = gl < b.na ? scnt[gl] : 0;
-        unsigned long long small = __ballot(nl > 0 && nl <= G);
+        unsigned long long small = __ballot(nl > NLO && nl <= G);
         while (small) {
-            // the next four small rows of the chunk, one per group of 16 lanes
+            // the next 64 / G rows of the chunk, one per group of G lanes
             int pick = -1;
 #pragma unroll
             for (int j = 0; j < kWave / G; ++j) {
@@ -650,8 +651,10 @@ void launch_sym_expand(const Batch &b, const Sched &sc, hipStream_t s)
     if (b.na <= 0 || !sc.scr) return;
     static int cus = device_cu_count();
     {
+        // rows of 1-16 words take 16 lanes each (4 rows per step), rows of 17-32 words 32 lanes
         ProfScope ps("sym_expand_small", s);
-        hipLaunchKernelGGL(k_sym_expand_small, dim3(cus * 8), dim3(kWG), 0, s, b, sc);
+        hipLaunchKernelGGL((k_sym_expand_small<kExpandSmall, 0>), dim3(cus * 8), dim3(kWG), 0, s, b, sc);
+        hipLaunchKernelGGL((k_sym_expand_small<kExpandMid, kExpandSmall>), dim3(cus * 8), dim3(kWG), 0, s, b, sc);
     }
     ProfScope ps("sym_expand", s);
     hipLaunchKernelGGL(k_sym_expand, dim3(cus * 8), dim3(kWG), 0, s, b, sc);
