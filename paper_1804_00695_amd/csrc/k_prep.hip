@@ -515,37 +515,38 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
 __global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
 {
     __shared__ int64_t s_red[kWG / kWave];
-    __shared__ int64_t s_tot[kNumBins];
+    __shared__ int64_t s_start[kNumBins];
     __shared__ int64_t s_carry;
     MLS_G int32_t *blk = gpw(sc.blk_cnt);
     const int stride = sc.nblk;
     const int nblk = nb < stride ? nb : stride;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = 0; c < kNumBins; ++c) {
-        int64_t v = 0;
-        for (int x = threadIdx.x; x < nblk; x += kWG) v += blk[c * stride + x];
-        v = group_sum<kWave>(v);
-        if (lane == 0) s_red[wave] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t t = 0;
-            for (int w = 0; w < kWG / kWave; ++w) t += s_red[w];
-            s_tot[c] = t;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < kNumBins) gpw(sc.bin_count)[threadIdx.x] = (int32_t)s_tot[threadIdx.x];
+    constexpr int kPer = 8;   // consecutive blocks per thread and step
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
-    constexpr int kPer = 8;   // consecutive blocks per thread and step
+    // bins in order, the running position spanning them: every block's count
+    // becomes the position in perm where its rows of the bin start; a bin's
+    // total is the difference of the positions where it and the next begin.
+    // With at most kWG * kPer blocks, all bins' counts are loaded up front.
+    const bool one_step = nblk <= kWG * kPer;
+    int32_t pre[kNumBins][kPer];
+    if (one_step) {
+        const int xb = threadIdx.x * kPer;
+#pragma unroll
+        for (int c = 0; c < kNumBins; ++c)
+#pragma unroll
+            for (int d = 0; d < kPer; ++d) pre[c][d] = xb + d < nblk ? blk[c * stride + xb + d] : 0;
+    }
+#pragma unroll
     for (int c = 0; c < kNumBins; ++c) {
+        if (threadIdx.x == 0) s_start[c] = s_carry;
         for (int x0 = 0; x0 < nblk; x0 += kWG * kPer) {
             const int xb = x0 + threadIdx.x * kPer;
             int32_t v[kPer];
             int64_t sum = 0;
 #pragma unroll
             for (int d = 0; d < kPer; ++d) {
-                v[d] = xb + d < nblk ? blk[c * stride + xb + d] : 0;
+                v[d] = one_step ? pre[c][d] : (xb + d < nblk ? blk[c * stride + xb + d] : 0);
                 sum += v[d];
             }
             int64_t incl = sum;
@@ -571,6 +572,12 @@ __global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
             }
             __syncthreads();
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumBins) {
+        const int c = threadIdx.x;
+        const int64_t end = c + 1 < kNumBins ? s_start[c + 1] : s_carry;
+        gpw(sc.bin_count)[c] = (int32_t)(end - s_start[c]);
     }
 }
 
