@@ -34,6 +34,7 @@ __global__ void k_fill_f64(double *p, double v, int64_t n)
 // (32) entries are checked by 16 (32) lanes each, four (two) at a time; the
 // wave checks longer rows together, one at a time, 64 entries per step.
 constexpr int kShortRow = 4;
+constexpr int kLongAhead = 4;   // long rows: steps of 64 entries whose loads are issued together
 
 // 64 / GL rows per step, GL lanes per row (rows of at most GL entries); mm
 // holds the lanes that own such rows. A row's verdict goes to its owner lane.
@@ -134,14 +135,25 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
         const MLS_G int32_t *c = (const MLS_G int32_t *)pa;
         int carry = -1;
         bool bl = false;
-        for (int q0 = 0; q0 < n; q0 += kWave) {
-            const int q = q0 + lane;
-            const bool valid = q < n;
-            const int cq = valid ? c[q] : 0;
-            int prev = __shfl_up(cq, 1, kWave);
-            if (lane == 0) prev = carry;
-            if (valid && (cq < 0 || cq >= nc || cq <= prev)) bl = true;
-            carry = __shfl(cq, kWave - 1, kWave);
+        for (int q4 = 0; q4 < n; q4 += kLongAhead * kWave) {
+            // the loads of kLongAhead steps first
+            int cqv[kLongAhead];
+#pragma unroll
+            for (int u = 0; u < kLongAhead; ++u) {
+                const int q = q4 + u * kWave + lane;
+                cqv[u] = q < n ? c[q] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kLongAhead; ++u) {
+                const int q0 = q4 + u * kWave;
+                if (q0 >= n) break;
+                const bool valid = q0 + lane < n;
+                const int cq = cqv[u];
+                int prev = __shfl_up(cq, 1, kWave);
+                if (lane == 0) prev = carry;
+                if (valid && (cq < 0 || cq >= nc || cq <= prev)) bl = true;
+                carry = __shfl(cq, kWave - 1, kWave);
+            }
         }
         if (__ballot(bl)) bad = bad || lane == src;
     }
@@ -289,10 +301,23 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
         int32_t *cp = (int32_t *)rl64(cnt_ptr);
         uint32_t carry_set = kNone, carry_msk = 0;
         int nout = 0;
+        uint32_t cvv[kLongAhead];
         for (int c0 = 0; c0 < n; c0 += kWave) {
+            const int u = (c0 / kWave) % kLongAhead;
+            if (u == 0) {   // the loads of the next kLongAhead steps
+#pragma unroll
+                for (int v = 0; v < kLongAhead; ++v) {
+                    const int qv = c0 + v * kWave + lane;
+                    cvv[v] = qv < n ? (uint32_t)c[qv] : 0u;
+                }
+            }
             const int q = c0 + lane;
             const bool valid = q < n;
-            const uint32_t cv = valid ? (uint32_t)c[q] : 0u;
+            uint32_t cv = 0u;
+#pragma unroll
+            for (int v = 0; v < kLongAhead; ++v)
+                if (v == u) cv = cvv[v];
+            cv = valid ? cv : 0u;
             const uint32_t set = valid ? (cv >> 5) : kNone;
             uint32_t prev = __shfl_up(set, 1, kWave);
             if (lane == 0) prev = carry_set;
