@@ -77,7 +77,10 @@ typedef enum {
     SPGEMM_OPT_VALIDATE = 0,      /* 1 (default): the symbolic phase checks A and B on the device */
     SPGEMM_OPT_FORCE_SPILL = 1,   /* 1: every row takes the global-memory accumulator path (test knob) */
     SPGEMM_OPT_GROUP_SIZE = 2,    /* 0 (default): lanes per row chosen from row lengths; else 8/16/32/64 */
-    SPGEMM_OPT_UNROLL = 3,        /* reserved */
+    SPGEMM_OPT_FORCE_CLASS = 3,   /* -1 (default): rows binned by size; c in 0..4: every row of the
+                                     symbolic, numeric and adjoint phases whose size class is below c
+                                     runs in LDS class c instead (test knob: every class kernel then
+                                     sees rows of every size; results are unchanged) */
     SPGEMM_OPT_PROFILE = 4,       /* 1: time every kernel launch with a HIP event pair on its stream */
     SPGEMM_OPT_WIDE_TABLE = 5     /* 1: the numeric phase keeps 8-byte (column, position) hash slots
                                      even where column and position fit one 32-bit slot (test knob) */
@@ -163,8 +166,9 @@ spgemm_status spgemm_symbolic(const spgemm_csr *A, const spgemm_csr *B, int32_t 
 spgemm_status spgemm_numeric(const spgemm_csr *A, const spgemm_csr *B, spgemm_csr *C,
                              void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Reports and clears the device-side error flag of a workspace after the
- * stream has finished (synchronises the stream). */
+/* Reports and clears the device-side error flag of a workspace (the word at
+ * its start) after the work queued on the stream has finished (synchronises
+ * the stream). */
 spgemm_status spgemm_check_errors(void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
@@ -293,16 +297,26 @@ void spgemm_batch_plan_destroy(spgemm_batch_plan *plan);
  * Adjoint (backward) of loss = sum_ij W_ij (A*B)_ij
  * --------------------------------------------------------------------- */
 
+/* Workspace for spgemm_backward in the given mode (deterministic != 0: the
+ * transpose of A with its values plus the transpose's scratch; otherwise the
+ * row binning of W). */
 spgemm_status spgemm_backward_workspace_size(const spgemm_csr *A, const spgemm_csr *B,
-                                             const spgemm_csr *W, size_t *bytes);
+                                             const spgemm_csr *W, int32_t deterministic, size_t *bytes);
 /* W holds dLoss/dC on the pattern of C = A*B (its row_ptr/col_idx are C's).
  * dA_values[nnz(A)] receives dA_ik = sum_j W_ij b_kj (masked to pat(A));
- * dB_values[nnz(B)] receives dB_kj = sum_i a_ik W_ij (masked to pat(B)),
- * accumulated with device atomics (order of the sum not fixed). Either
- * output may be NULL. Does not synchronise. */
+ * dB_values[nnz(B)] receives dB_kj = sum_i a_ik W_ij (masked to pat(B)).
+ * Either output may be NULL. Does not synchronise.
+ *   deterministic == 0: fused kernel, dB accumulated with device atomics, so
+ *     the order of dB's sums (and its last bits) may change between calls.
+ *   deterministic != 0: each entry is one sequential sum in a fixed order
+ *     (dA_ik over j ascending; dB_kj over i ascending, gathered through the
+ *     transpose of A), products rounded before they are added; repeated calls
+ *     give identical bits.
+ * A column of A*B missing from W sets the structure error, which the next
+ * synchronising call (spgemm_check_errors) reports as SPGEMM_ERR_STRUCTURE. */
 spgemm_status spgemm_backward(const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *W,
-                              double *dA_values, double *dB_values, void *ws, size_t ws_bytes,
-                              hipStream_t stream);
+                              double *dA_values, double *dB_values, int32_t deterministic, void *ws,
+                              size_t ws_bytes, hipStream_t stream);
 
 /* CSR transpose of M into T (T shaped M.ncols x M.nrows, T.row_ptr/col_idx/
  * values allocated by the caller with nnz(M) entries); columns of T come out

@@ -41,6 +41,38 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None or t.numel() == 0 else t.data_ptr()
 
 
+def _check_array(t, name: str, dtype, numel: int, where: str):
+    """The array the kernels will read or write: right dtype, memory kind and
+    length, contiguous. `where` is "cuda" (device memory) or "pinned" (page-
+    locked host memory). Raises ValueError before any library call."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if where == "cuda" and t.device.type != "cuda":
+        raise ValueError(f"{name}: on {t.device}, expected a GPU tensor")
+    if where == "pinned" and (t.device.type != "cpu" or (t.numel() > 0 and not t.is_pinned())):
+        raise ValueError(f"{name}: expected pinned host memory (torch pin_memory)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+
+
+def _check_csr(M, where: str, need_values: bool = False):
+    if M.nrows < 0 or M.ncols < 0:
+        raise ValueError(f"negative shape {M.nrows} x {M.ncols}")
+    _check_array(M.row_ptr, "row_ptr", torch.int32, M.nrows + 1, where)
+    nnz = int(M.col_idx.numel()) if isinstance(M.col_idx, torch.Tensor) else -1
+    _check_array(M.col_idx, "col_idx", torch.int32, nnz, where)
+    if M.values is not None:
+        _check_array(M.values, "values", torch.float64, nnz, where)
+    elif need_values and nnz > 0:
+        raise ValueError("values are required here")
+    if where == "cuda" and M.row_ptr.device != M.col_idx.device:
+        raise ValueError("row_ptr and col_idx on different devices")
+
+
 @dataclass
 class DeviceCsr:
     """CSR matrix in device memory (int32 indices, fp64 values or None)."""
@@ -55,6 +87,8 @@ class DeviceCsr:
         return int(self.col_idx.numel())
 
     def handle(self) -> CsrT:
+        """C handle; checks dtypes, device, contiguity and lengths first."""
+        _check_csr(self, "cuda")
         return CsrT(self.nrows, self.ncols, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.values))
 
     @classmethod
@@ -86,6 +120,8 @@ class HostCsr:
         return int(self.col_idx.numel())
 
     def handle(self) -> CsrT:
+        """C handle; checks dtypes, pinning, contiguity and lengths first."""
+        _check_csr(self, "pinned")
         return CsrT(self.nrows, self.ncols, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.values))
 
     @classmethod
@@ -311,19 +347,36 @@ def triangle_count(L: DeviceCsr, ws: Optional[Workspace] = None):
 # ---------------------------------------------------------------------------
 # adjoint (backward) and its unfused per-call counterpart
 
+def backward_workspace_size(A: DeviceCsr, B: DeviceCsr, W: DeviceCsr, deterministic: bool = False) -> int:
+    n = ctypes.c_size_t(0)
+    check(lib.spgemm_backward_workspace_size(ctypes.byref(A.handle()), ctypes.byref(B.handle()),
+                                             ctypes.byref(W.handle()), int(deterministic), ctypes.byref(n)),
+          "spgemm_backward_workspace_size")
+    return n.value
+
+
 def backward(A: DeviceCsr, B: DeviceCsr, W: DeviceCsr, need_a: bool = True, need_b: bool = True,
-             ws: Optional[Workspace] = None):
-    """Fused adjoint of sum(W o (A*B)): (dA values on pat(A), dB values on pat(B))."""
+             ws: Optional[Workspace] = None, deterministic: bool = False, check_structure: bool = True):
+    """Fused adjoint of sum(W o (A*B)): (dA values on pat(A), dB values on pat(B)).
+
+    deterministic: dB by a gather over the transpose of A (each entry's terms in
+    ascending row order, repeatable bit for bit) instead of device atomics.
+    check_structure: read the device error word back afterwards (one 4-byte
+    copy and a stream synchronisation) and raise when W misses a column of
+    A*B."""
     dev = A.row_ptr.device
     w = _ws(ws, dev)
-    n = ctypes.c_size_t(0)
     ha, hb, hw = A.handle(), B.handle(), W.handle()
-    check(lib.spgemm_backward_workspace_size(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(hw), ctypes.byref(n)),
-          "spgemm_backward_workspace_size")
+    if A.values is None or B.values is None or W.values is None:
+        raise ValueError("backward needs the values of A, B and W")
+    nb = backward_workspace_size(A, B, W, deterministic)
     dA = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=dev) if need_a else None
     dB = torch.empty(max(B.nnz, 1), dtype=torch.float64, device=dev) if need_b else None
+    p = w.get(nb)
     check(lib.spgemm_backward(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(hw), _ptr(dA), _ptr(dB),
-                              w.get(n.value), n.value, stream_handle()), "spgemm_backward")
+                              int(deterministic), p, nb, stream_handle()), "spgemm_backward")
+    if check_structure:
+        check(lib.spgemm_check_errors(p, nb, stream_handle()), "spgemm_backward")
     return (None if dA is None else dA[:A.nnz]), (None if dB is None else dB[:B.nnz])
 
 
@@ -361,22 +414,36 @@ def backward_unfused(A: DeviceCsr, B: DeviceCsr, W: DeviceCsr, ws: Optional[Work
 
 class SpGEMMFn(torch.autograd.Function):
     """c_values = values of A*B on a fixed structure; differentiable in the
-    values of A and B (structures are constants)."""
+    values of A and B (structures are constants). Both directions read the
+    library's device error word back, so a structure of C that misses a
+    column A*B reaches raises instead of giving wrong values."""
 
     @staticmethod
     def forward(ctx, a_values, b_values, A, B, C):
-        A2 = DeviceCsr(A.nrows, A.ncols, A.row_ptr, A.col_idx, a_values.detach().contiguous())
-        B2 = DeviceCsr(B.nrows, B.ncols, B.row_ptr, B.col_idx, b_values.detach().contiguous())
+        _check_array(a_values, "a_values", torch.float64, A.nnz, "cuda")
+        _check_array(b_values, "b_values", torch.float64, B.nnz, "cuda")
+        av, bv = a_values.detach(), b_values.detach()
+        A2 = DeviceCsr(A.nrows, A.ncols, A.row_ptr, A.col_idx, av)
+        B2 = DeviceCsr(B.nrows, B.ncols, B.row_ptr, B.col_idx, bv)
         C2 = DeviceCsr(C.nrows, C.ncols, C.row_ptr, C.col_idx,
                        torch.empty(C.nnz, dtype=torch.float64, device=a_values.device))
-        numeric(A2, B2, C2)
-        ctx.A, ctx.B, ctx.C = A2, B2, C2
+        ws = _ws(None, a_values.device)
+        numeric(A2, B2, C2, ws)
+        check_errors(ws, a_values.device)
+        # saved through autograd, so an in-place change of the inputs after
+        # the forward pass is detected instead of silently changing dB / dA
+        ctx.save_for_backward(a_values, b_values)
+        ctx.shapes = (A, B, C)
         return C2.values
 
     @staticmethod
     def backward(ctx, grad_c):
-        W = DeviceCsr(ctx.C.nrows, ctx.C.ncols, ctx.C.row_ptr, ctx.C.col_idx, grad_c.contiguous())
-        dA, dB = backward(ctx.A, ctx.B, W, need_a=ctx.needs_input_grad[0], need_b=ctx.needs_input_grad[1])
+        a_values, b_values = ctx.saved_tensors
+        A, B, C = ctx.shapes
+        A2 = DeviceCsr(A.nrows, A.ncols, A.row_ptr, A.col_idx, a_values.detach())
+        B2 = DeviceCsr(B.nrows, B.ncols, B.row_ptr, B.col_idx, b_values.detach())
+        W = DeviceCsr(C.nrows, C.ncols, C.row_ptr, C.col_idx, grad_c.contiguous())
+        dA, dB = backward(A2, B2, W, need_a=ctx.needs_input_grad[0], need_b=ctx.needs_input_grad[1])
         return dA, dB, None, None, None
 
 

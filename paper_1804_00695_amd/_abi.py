@@ -70,14 +70,14 @@ SIGNATURES = {
     "spgemm_batch_plan_run": (ctypes.c_int, [P, P]),
     "spgemm_batch_plan_group_size": (c_int32, [P]),
     "spgemm_batch_plan_destroy": (None, [P]),
-    "spgemm_backward_workspace_size": (ctypes.c_int, [CSRP, CSRP, CSRP, SZP]),
-    "spgemm_backward": (ctypes.c_int, [CSRP, CSRP, CSRP, P, P, P, c_size_t, P]),
+    "spgemm_backward_workspace_size": (ctypes.c_int, [CSRP, CSRP, CSRP, c_int32, SZP]),
+    "spgemm_backward": (ctypes.c_int, [CSRP, CSRP, CSRP, P, P, c_int32, P, c_size_t, P]),
     "spgemm_transpose_workspace_size": (ctypes.c_int, [CSRP, SZP]),
     "spgemm_transpose": (ctypes.c_int, [CSRP, CSRP, P, c_size_t, P]),
     "spgemm_mask_gather": (ctypes.c_int, [CSRP, CSRP, P, P]),
 }
 
-OPT_VALIDATE, OPT_FORCE_SPILL, OPT_GROUP_SIZE, OPT_PROFILE, OPT_WIDE_TABLE = 0, 1, 2, 4, 5
+OPT_VALIDATE, OPT_FORCE_SPILL, OPT_GROUP_SIZE, OPT_FORCE_CLASS, OPT_PROFILE, OPT_WIDE_TABLE = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = ["OK", "INVALID_ARG", "BAD_CSR", "DIM_MISMATCH", "INDEX_OVERFLOW", "WORKSPACE_TOO_SMALL",
                 "BUDGET", "HIP", "UNSUPPORTED", "STRUCTURE"]
 

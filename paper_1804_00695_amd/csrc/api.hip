@@ -273,7 +273,7 @@ spgemm_status run_symbolic(BatchHost &bh, char *ws, int fill, int64_t *nnz_host,
         if (st != SPGEMM_OK) return st;
     }
     if (!reuse) launch_compress(bh.batch, s);
-    launch_bin(bh.batch, fill ? kModeFill : kModeCount, sc, (int)g_opt.force_spill, nullptr, s);
+    launch_bin(bh.batch, fill ? kModeFill : kModeCount, sc, bin_force(), nullptr, s);
     if (fill) launch_sym_expand(bh.batch, sc, s);
     launch_symbolic(bh.batch, sc, fill, choose_group(bh.avg_a), s);
     spgemm_status st = check_launch();
@@ -318,7 +318,7 @@ spgemm_status run_numeric(BatchHost &bh, char *ws, hipStream_t s)
     const Layout &L = bh.layout;
     Sched sc = make_sched(ws, L);
     reset_header(ws, L, s);
-    launch_bin(bh.batch, kModeNumeric, sc, (int)g_opt.force_spill, nullptr, s);
+    launch_bin(bh.batch, kModeNumeric, sc, bin_force(), nullptr, s);
     launch_numeric(bh.batch, sc, choose_group(bh.avg_b), s);
     return check_launch();
 }
@@ -360,7 +360,10 @@ spgemm_status spgemm_set_option(spgemm_option opt, int64_t value)
         if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64) return SPGEMM_ERR_INVALID_ARG;
         g_opt.group_size = value;
         return SPGEMM_OK;
-    case SPGEMM_OPT_UNROLL: return SPGEMM_OK;
+    case SPGEMM_OPT_FORCE_CLASS:
+        if (value < -1 || value >= kNumClasses) return SPGEMM_ERR_INVALID_ARG;
+        g_opt.force_class = (int)value;
+        return SPGEMM_OK;
     case SPGEMM_OPT_PROFILE: g_opt.profile = value != 0; return SPGEMM_OK;
     case SPGEMM_OPT_WIDE_TABLE: g_opt.wide_table = value != 0; return SPGEMM_OK;
     }
@@ -375,6 +378,7 @@ int64_t spgemm_get_option(spgemm_option opt)
     case SPGEMM_OPT_GROUP_SIZE: return g_opt.group_size;
     case SPGEMM_OPT_PROFILE: return g_opt.profile;
     case SPGEMM_OPT_WIDE_TABLE: return g_opt.wide_table;
+    case SPGEMM_OPT_FORCE_CLASS: return g_opt.force_class;
     default: return 0;
     }
 }
@@ -511,7 +515,14 @@ spgemm_status spgemm_check_errors(void *ws, size_t ws_bytes, hipStream_t stream)
     Layout L;
     std::memset(&L, 0, sizeof(L));
     L.hdr = 0;
-    return read_errors((char *)ws, L, stream);
+    spgemm_status st = read_errors((char *)ws, L, stream);
+    if (st == SPGEMM_OK || st == SPGEMM_ERR_BAD_CSR || st == SPGEMM_ERR_INDEX_OVERFLOW ||
+        st == SPGEMM_ERR_STRUCTURE) {
+        launch_fill_i32((int32_t *)((char *)ws + kHdrErr), 0, 1, stream);
+        spgemm_status st2 = check_launch();
+        if (st == SPGEMM_OK) st = st2;
+    }
+    return st;
 }
 
 }  // extern "C"

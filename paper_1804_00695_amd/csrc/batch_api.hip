@@ -86,7 +86,7 @@ spgemm_status spgemm_batch_plan_create(int32_t nbatch, const spgemm_csr *A, cons
     P->ws = (char *)ws;
     Sched sc = make_sched(P->ws, P->bh.layout);
     reset_header(P->ws, P->bh.layout, s);
-    launch_bin(P->bh.batch, kModeNumeric, sc, (int)g_opt.force_spill, nullptr, s);
+    launch_bin(P->bh.batch, kModeNumeric, sc, bin_force(), nullptr, s);
     st = check_launch();
     if (st != SPGEMM_OK) { delete P; return st; }
     int64_t za = 0, zc = 0;

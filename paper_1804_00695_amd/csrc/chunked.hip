@@ -59,6 +59,22 @@ struct Ev {
     hipError_t wait(hipStream_t s) const { return recorded ? hipStreamWaitEvent(s, e, 0) : hipSuccess; }
 };
 
+// Bytes an A/C part [r0, r1) occupies in its buffer (each array on a
+// 256-byte boundary), and the same for a B part.
+size_t ac_extent(const spgemm_csr *A, const spgemm_csr *C, int32_t r0, int32_t r1)
+{
+    const size_t na = (size_t)((int64_t)A->row_ptr[r1] - A->row_ptr[r0]);
+    const size_t nc = (size_t)((int64_t)C->row_ptr[r1] - C->row_ptr[r0]);
+    const size_t rows = (size_t)(r1 - r0 + 1);
+    return 2 * al(4 * rows) + al(4 * na) + al(8 * na) + al(4 * nc) + 8 * nc;
+}
+
+size_t b_extent(const spgemm_csr *B, int32_t r0, int32_t r1)
+{
+    const size_t nb = (size_t)((int64_t)B->row_ptr[r1] - B->row_ptr[r0]);
+    return al(4 * (size_t)(r1 - r0 + 1)) + al(4 * nb) + 8 * nb;
+}
+
 void place_ac(AcBuf &b, const spgemm_csr *A, const spgemm_csr *C, int32_t r0, int32_t r1)
 {
     b.r0 = r0;
@@ -86,6 +102,15 @@ void place_b(BBuf &b, const spgemm_csr *B, int32_t r0, int32_t r1)
     b.bval = (double *)p;
 }
 
+// Host row pointers of an operand: start at 0, never decrease, end at nnz.
+bool row_ptr_ok(const int32_t *rp, int32_t n, int64_t nnz)
+{
+    if (rp[0] != 0) return false;
+    for (int32_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return false;
+    return (int64_t)rp[n] == nnz;
+}
+
 }  // namespace
 
 namespace mls {
@@ -96,7 +121,7 @@ spgemm_status numeric_launch(const Batch &b, double avg_b, char *ws, const Layou
     // clear the scheduling counters but keep the error word, so that errors
     // of every part accumulate until the end of the chunked run
     launch_fill_i32((int32_t *)(ws + L.hdr + kHdrBinCount), 0, (kHdrBytes - kHdrBinCount) / 4, s);
-    launch_bin(b, kModeNumeric, sc, (int)g_opt.force_spill, nullptr, s);
+    launch_bin(b, kModeNumeric, sc, bin_force(), nullptr, s);
     launch_numeric(b, sc, choose_group(avg_b), s);
     return check_launch();
 }
@@ -117,6 +142,12 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
         return SPGEMM_ERR_INVALID_ARG;
     if ((int64_t)ws_bytes < P->ws_bytes) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
     if (((uintptr_t)ws_v & 255) != 0) return SPGEMM_ERR_INVALID_ARG;
+    // the operands must be the ones the plan was cut for: same entry counts
+    // and consistent row pointers (the part buffers are sized from them)
+    if (A->nnz != P->nnzA || B->nnz != P->nnzB || C->nnz != P->nnzC) return SPGEMM_ERR_DIM_MISMATCH;
+    if (!row_ptr_ok(A->row_ptr, A->nrows, A->nnz) || !row_ptr_ok(B->row_ptr, B->nrows, B->nnz) ||
+        !row_ptr_ok(C->row_ptr, C->nrows, C->nnz))
+        return SPGEMM_ERR_BAD_CSR;
     char *ws = (char *)ws_v;
     memo_forget(ws_v);
 
@@ -137,7 +168,15 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
         need = al(L.total) + rb + P->nbuf_inner * rac;
     }
     if (need > ws_bytes) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
-    reset_header(ws, L, s_c);
+    // every part of the schedule must fit its buffer region before anything
+    // is queued
+    for (const spgemm_plan_step &stp : P->steps) {
+        if (stp.kind != kStepH2D) continue;
+        if (stp.row_begin < 0 || stp.row_end < stp.row_begin) return SPGEMM_ERR_INVALID_ARG;
+        if (stp.matrix == kMatA && ac_extent(A, C, stp.row_begin, stp.row_end) > rac)
+            return SPGEMM_ERR_DIM_MISMATCH;
+        if (stp.matrix == kMatB && b_extent(B, stp.row_begin, stp.row_end) > rb) return SPGEMM_ERR_DIM_MISMATCH;
+    }
 
     Ev ev_b_ready[2], ev_ac_ready[2], ev_kdone[2], ev_d2h[2], ev_outer_free, ev_last_kernel, ev_last_d2h;
     Ev *all[] = {&ev_b_ready[0], &ev_b_ready[1], &ev_ac_ready[0], &ev_ac_ready[1], &ev_kdone[0], &ev_kdone[1],
@@ -150,6 +189,19 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
             if (x->e) hipEventDestroy(x->e);
     };
     if (e != hipSuccess) { cleanup(); return hip_fail(e); }
+    // the copy streams must not overwrite the workspace while work queued
+    // earlier on the compute stream (an in-HBM product on the same
+    // workspace, for instance) still reads it
+    {
+        Ev entry;
+        e = hipEventCreateWithFlags(&entry.e, hipEventDisableTiming);
+        if (e == hipSuccess) e = entry.record(s_c);
+        if (e == hipSuccess) e = entry.wait(s_h);
+        if (e == hipSuccess) e = entry.wait(s_d);
+        if (entry.e) hipEventDestroy(entry.e);
+        if (e != hipSuccess) { cleanup(); return hip_fail(e); }
+    }
+    reset_header(ws, L, s_c);
 
     const double avg_b = B->nrows > 0 ? (double)B->nnz / B->nrows : 1.0;
     int64_t issued_h = 0, issued_d = 0;

@@ -17,8 +17,13 @@ struct Options {
     bool wide_table = false;
     int64_t group_size = 0;
     bool profile = false;
+    int force_class = -1;   // test knob: rows move up to this LDS class (-1: off)
 };
 extern Options g_opt;
+
+// Binning override handed to the binning kernels: kBinSpill when every row
+// must spill, else the forced class floor (-1 = natural classes).
+inline int bin_force() { return g_opt.force_spill ? kBinSpill : g_opt.force_class; }
 extern thread_local int g_last_hip_error;
 
 // Header region at the start of every workspace.

@@ -438,6 +438,94 @@ void launch_backward(const Batch &b, const Sched &sc, const double *wval, double
 }
 
 // ---------------------------------------------------------------------------
+// Deterministic adjoint: every entry of dA and of dB is the sequential sum of
+// one lane, in the order of the row-wise formulation -- dA_ik over the columns
+// j of B_k in ascending order, dB_kj over the rows i of column k of A in
+// ascending order (read from the transpose of A) -- with each product rounded
+// before it is added. The result does not depend on scheduling, so repeated
+// calls agree bit for bit. W_ij is found by binary search in W_i's ascending
+// columns (no LDS table, no atomics on the outputs); a triple whose column j
+// is missing from W_i sets the structure error.
+
+constexpr int kDetLanes = 8;   // lanes per row; a lane takes every 8th entry
+
+__global__ __launch_bounds__(kWG) void k_bwd_det_da(int32_t m, const int32_t *arp, const int32_t *aci,
+                                                    const int32_t *brp, const int32_t *bci, const double *bval,
+                                                    const int32_t *wrp, const int32_t *wci, const double *wval,
+                                                    double *dA, uint32_t *err)
+{
+    const int64_t g = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int64_t i = g / kDetLanes;
+    if (i >= m) return;
+    const int l = (int)(g % kDetLanes);
+    const int ws = gp(wrp)[i], wn = gp(wrp)[i + 1] - ws;
+    const MLS_G int32_t *wc = gp(wci) + ws;
+    const MLS_G double *wv = gp(wval) + ws;
+    bool bad = false;
+    const int pe = gp(arp)[i + 1];
+    for (int p = gp(arp)[i] + l; p < pe; p += kDetLanes) {
+        const int k = gp(aci)[p];
+        const int qs = gp(brp)[k], qe = gp(brp)[k + 1];
+        double sum = 0.0;
+        int lo = 0;   // the columns of B_k ascend, so each search starts past the last hit
+        for (int q = qs; q < qe; ++q) {
+            const int j = gp(bci)[q];
+            lo = lower_col_w(wc, lo, wn, j);
+            if (lo >= wn || wc[lo] != j) { bad = true; break; }
+            sum += wv[lo] * gp(bval)[q];
+        }
+        gpw(dA)[p] = sum;
+    }
+    if (bad) atomicOr(err, kErrStructure);
+}
+
+__global__ __launch_bounds__(kWG) void k_bwd_det_db(int32_t kb, const int32_t *trp, const int32_t *tci,
+                                                    const double *tv, const int32_t *brp, const int32_t *bci,
+                                                    const int32_t *wrp, const int32_t *wci, const double *wval,
+                                                    double *dB, uint32_t *err)
+{
+    const int64_t g = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const int64_t k = g / kDetLanes;
+    if (k >= kb) return;
+    const int l = (int)(g % kDetLanes);
+    const int rs = gp(trp)[k], re = gp(trp)[k + 1];
+    bool bad = false;
+    const int qe = gp(brp)[k + 1];
+    for (int q = gp(brp)[k] + l; q < qe; q += kDetLanes) {
+        const int j = gp(bci)[q];
+        double sum = 0.0;
+        for (int r = rs; r < re; ++r) {   // rows i of column k of A, ascending
+            const int i = gp(tci)[r];
+            const int ws = gp(wrp)[i], wn = gp(wrp)[i + 1] - ws;
+            const int pos = lower_col_w(gp(wci) + ws, 0, wn, j);
+            if (pos >= wn || gp(wci)[ws + pos] != j) { bad = true; break; }
+            sum += gp(tv)[r] * gp(wval)[ws + pos];
+        }
+        gpw(dB)[q] = sum;
+    }
+    if (bad) atomicOr(err, kErrStructure);
+}
+
+void launch_backward_det(int32_t m, int32_t kb, const int32_t *arp, const int32_t *aci, const int32_t *brp,
+                         const int32_t *bci, const double *bval, const int32_t *wrp, const int32_t *wci,
+                         const double *wval, const int32_t *trp, const int32_t *tci, const double *tv, double *dA,
+                         double *dB, uint32_t *err, hipStream_t s)
+{
+    if (dA && m > 0) {
+        ProfScope ps("bwd_det_dA", s);
+        const int64_t blocks = ((int64_t)m * kDetLanes + kWG - 1) / kWG;
+        hipLaunchKernelGGL(k_bwd_det_da, dim3((unsigned)blocks), dim3(kWG), 0, s, m, arp, aci, brp, bci, bval, wrp,
+                           wci, wval, dA, err);
+    }
+    if (dB && kb > 0) {
+        ProfScope ps("bwd_det_dB", s);
+        const int64_t blocks = ((int64_t)kb * kDetLanes + kWG - 1) / kWG;
+        hipLaunchKernelGGL(k_bwd_det_db, dim3((unsigned)blocks), dim3(kWG), 0, s, kb, trp, tci, tv, brp, bci, wrp,
+                           wci, wval, dB, err);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // transpose
 
 __global__ void k_tr_count(int32_t nrows, const int32_t *rp, const int32_t *ci, int32_t *cnt)

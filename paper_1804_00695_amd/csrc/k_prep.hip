@@ -375,18 +375,23 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
 //   kModeWork   : size = sum over in-range k of nnz(B_k) (multiply-adds)
 // Threshold classes: kCountCap for count, kFillCap/2 for fill and numeric.
 
-__device__ __forceinline__ int class_of(int mode, int64_t size, int force_spill)
+// force < 0: natural class; force = kBinSpill: every non-empty row spills;
+// 0 <= force < kNumClasses: rows of a smaller natural class move up to class
+// `force` (a larger table always holds a row; test knob).
+__device__ __forceinline__ int class_of(int mode, int64_t size, int force)
 {
     if (size == 0) return kBinEmpty;
-    if (force_spill) return kBinSpill;
+    if (force == kBinSpill) return kBinSpill;
+    int cls = kBinSpill;
     if (mode == kModeCount) {
         for (int c = 0; c < kNumClasses; ++c)
-            if (size <= kCountCap[c]) return c;
+            if (size <= kCountCap[c]) { cls = c; break; }
     } else {
         for (int c = 0; c < kNumClasses; ++c)
-            if (size <= kFillCap[c] / 2) return c;
+            if (size <= kFillCap[c] / 2) { cls = c; break; }
     }
-    return kBinSpill;
+    if (force >= 0 && cls < force) cls = force;
+    return cls;
 }
 
 constexpr int kBinRG = 4;                    // lanes per row where the size is gathered (measured: 2-16)
@@ -401,7 +406,7 @@ __device__ __forceinline__ void bin_write_counts(const Sched &sc, const int *cnt
 }
 
 // Bin of a row of known size (count, fill and work modes), by one thread.
-__device__ __forceinline__ void bin_place(int mode, const Sched &sc, int force_spill, const Prob &P, int g, int i,
+__device__ __forceinline__ void bin_place(int mode, const Sched &sc, int force, const Prob &P, int g, int i,
                                           bool from_scratch, int64_t size, int *cnt, unsigned long long *tsum)
 {
     int c;
@@ -417,7 +422,7 @@ __device__ __forceinline__ void bin_place(int mode, const Sched &sc, int force_s
             if (size >= 0x7fffffffLL) atomicOr(sc.err, kErrOverflow);
             atomicAdd(tsum, (unsigned long long)size);
         } else {
-            c = class_of(mode, size, force_spill);
+            c = class_of(mode, size, force);
             // a large row whose dense bitmap over C's columns is at most half
             // its class table takes the spill path's LDS bitmap instead
             if (c >= 3 && c < kNumClasses &&
@@ -433,7 +438,7 @@ __device__ __forceinline__ void bin_place(int mode, const Sched &sc, int force_s
     atomicAdd(&cnt[c], 1);
 }
 
-__global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int force_spill,
+__global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int force,
                                              unsigned long long *total)
 {
     __shared__ int cnt[kNumBins];
@@ -454,7 +459,7 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
             const Prob P = get_prob(b, t);
             const int i = g - (b.nprob == 1 ? 0 : pc.lo);
             const int nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
-            const int c = class_of(mode, nc, force_spill);
+            const int c = class_of(mode, nc, force);
             gpw(sc.val)[g] = nc;
             gpw(sc.cls)[g] = (uint8_t)c;
             atomicAdd(&cnt[c], 1);
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
             }
             size = group_sum<kBinRG>(size);
         }
-        if (lane == 0) bin_place(mode, sc, force_spill, P, g, i, from_scratch, size, cnt, &tsum);
+        if (lane == 0) bin_place(mode, sc, force, P, g, i, from_scratch, size, cnt, &tsum);
     }
     __syncthreads();
     // the deferred long rows, one at a time across the workgroup
@@ -524,7 +529,7 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
         if (threadIdx.x == 0) {
             int64_t tot = 0;
             for (int w = 0; w < kWG / kWave; ++w) tot += s_red[w];
-            bin_place(mode, sc, force_spill, P, g, i, false, tot, cnt, &tsum);
+            bin_place(mode, sc, force, P, g, i, false, tot, cnt, &tsum);
         }
         __syncthreads();
     }
@@ -773,13 +778,13 @@ void launch_compress(const Batch &b, hipStream_t s)
     hipLaunchKernelGGL(k_compress, dim3(nblk(b.nb, kWG)), dim3(kWG), 0, s, b);
 }
 
-void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsigned long long *total,
+void launch_bin(const Batch &b, int mode, const Sched &sc, int force, unsigned long long *total,
                 hipStream_t s)
 {
     if (b.na <= 0) return;
     {
         ProfScope ps("bin", s);
-        hipLaunchKernelGGL(k_bin, dim3(nblk(b.na, kBinRowsPerWG)), dim3(kWG), 0, s, b, mode, sc, force_spill, total);
+        hipLaunchKernelGGL(k_bin, dim3(nblk(b.na, kBinRowsPerWG)), dim3(kWG), 0, s, b, mode, sc, force, total);
     }
     launch_scatter(b.na, sc, s);
 }

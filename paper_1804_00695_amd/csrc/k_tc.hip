@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kWG) void k_tc_spill(Batch b, Sched sc, int64_t *co
 
 // Bins of L's rows by the word count of row i itself (the size of its hash
 // table); rows without entries count zero triangles.
-__global__ __launch_bounds__(kWG) void k_tc_bin(Batch b, Sched sc, int force_spill)
+__global__ __launch_bounds__(kWG) void k_tc_bin(Batch b, Sched sc, int force)
 {
     __shared__ int cnt[kNumBins];
     if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
@@ -298,11 +298,12 @@ __global__ __launch_bounds__(kWG) void k_tc_bin(Batch b, Sched sc, int force_spi
         int size = gp(P.bwc)[i];
         int c;
         if (len == 0) c = kBinEmpty;
-        else if (force_spill) c = kBinSpill;
+        else if (force == kBinSpill) c = kBinSpill;
         else {
             c = kBinSpill;
             for (int x = kNumClasses - 1; x >= 0; --x)
                 if (size <= kTcCap[x] / 2) c = x;
+            if (force >= 0 && c < force) c = force;   // test knob: a larger table holds any row
         }
         gpw(sc.val)[i] = size;
         gpw(sc.cls)[i] = (uint8_t)c;
@@ -349,13 +350,13 @@ static void launch_tc_class(const Batch &b, const Sched &sc, int bin, int64_t *c
     hipLaunchKernelGGL((k_tc_lds<G, CAP, P, PP, WPE>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, counts);
 }
 
-void launch_tc_bin(const Batch &b, const Sched &sc, int force_spill, hipStream_t s)
+void launch_tc_bin(const Batch &b, const Sched &sc, int force, hipStream_t s)
 {
     if (b.na <= 0) return;
     int grid = (b.na + kBinRowsPerWG - 1) / kBinRowsPerWG;
     {
         ProfScope ps("tc_bin", s);
-        hipLaunchKernelGGL(k_tc_bin, dim3(grid), dim3(kWG), 0, s, b, sc, force_spill);
+        hipLaunchKernelGGL(k_tc_bin, dim3(grid), dim3(kWG), 0, s, b, sc, force);
     }
     launch_scatter(b.na, sc, s);
 }

@@ -14,7 +14,7 @@ void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void launch_validate(const Batch &b, int which, const int64_t *nnz_tab, uint32_t *err, hipStream_t s);
 void launch_compress(const Batch &b, hipStream_t s);
-void launch_bin(const Batch &b, int mode, const Sched &sc, int force_spill, unsigned long long *total,
+void launch_bin(const Batch &b, int mode, const Sched &sc, int force, unsigned long long *total,
                 hipStream_t s);
 int scan_tiles(int n);
 void launch_scan(const int32_t *val, int n, int64_t *tile_sum, int64_t *prefix, hipStream_t s);
@@ -37,12 +37,19 @@ void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s);
 // Triangle counting over the binned rows of L (A = B = L in the batch).
 void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long long *total,
                uint32_t *spill_bitmaps, int spill_slots, int64_t spill_words, hipStream_t s);
-void launch_tc_bin(const Batch &b, const Sched &sc, int force_spill, hipStream_t s);
+void launch_tc_bin(const Batch &b, const Sched &sc, int force, hipStream_t s);
 void launch_scatter(int na, const Sched &sc, hipStream_t s);
 
 // Backward (adjoint) over the binned rows of W (= pattern of C).
 void launch_backward(const Batch &b, const Sched &sc, const double *wval, double *dA, double *dB, int G,
                      hipStream_t s);
+
+// Deterministic adjoint (one lane per output entry, sequential sums; W_ij by
+// binary search in W_i). trp/tci/tv: the transpose of A with its values.
+void launch_backward_det(int32_t m, int32_t kb, const int32_t *arp, const int32_t *aci, const int32_t *brp,
+                         const int32_t *bci, const double *bval, const int32_t *wrp, const int32_t *wci,
+                         const double *wval, const int32_t *trp, const int32_t *tci, const double *tv, double *dA,
+                         double *dB, uint32_t *err, hipStream_t s);
 
 // Transpose and masked gather helpers.
 void launch_transpose(int32_t nrows, int32_t ncols, const int32_t *rp, const int32_t *ci, const double *v,

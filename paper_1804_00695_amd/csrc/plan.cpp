@@ -210,6 +210,9 @@ spgemm_status spgemm_chunked_plan(const spgemm_csr *A, const spgemm_csr *B, cons
     P->nA = A->nrows;
     P->nB = B->nrows;
     P->ncols = B->ncols;
+    P->nnzA = A->row_ptr[A->nrows];
+    P->nnzB = B->row_ptr[B->nrows];
+    P->nnzC = C_row_ptr[A->nrows];
     // reserve: the numeric kernels' per-row arrays for up to all rows of A,
     // plus alignment slack of the part buffers
     P->reserve = (int64_t)make_layout(1, A->nrows, B->nrows, 0, B->ncols, false).total + kChunkSlack;

@@ -23,6 +23,7 @@ struct Part {
 struct PlanImpl {
     int algo = 0, branch = 0, nbuf_inner = 1;
     int32_t nA = 0, nB = 0, ncols = 0;
+    int64_t nnzA = 0, nnzB = 0, nnzC = 0;   // of the operands the plan was made for
     int64_t fast = 0, reserve = 0;
     std::vector<Part> p_ac, p_b;
     int64_t h2d = 0, d2h = 0, cost1 = 0, cost2 = 0;

@@ -96,7 +96,7 @@ spgemm_status spgemm_tc(const spgemm_csr *L, int64_t *counts, int64_t *total_hos
     }
     unsigned long long *tot = (unsigned long long *)(ws + Lay.hdr + kHdrTotal);
     launch_compress(bh.batch, s);
-    launch_tc_bin(bh.batch, sc, (int)g_opt.force_spill, s);
+    launch_tc_bin(bh.batch, sc, bin_force(), s);
     launch_tc(bh.batch, sc, counts, tot, (uint32_t *)(ws + Lay.spill), Lay.spill_slots, Lay.spill_words, s);
     st = check_launch();
     if (st != SPGEMM_OK) return st;

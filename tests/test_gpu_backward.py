@@ -114,3 +114,105 @@ def test_rmat_power_law_spill():
     rA, rB, aA, aB = oracle.backward(A, A, W)
     assert np.all(np.abs(dA.cpu().numpy() - rA) <= TOL * aA + 1e-300)
     assert np.all(np.abs(dB.cpu().numpy() - rB) <= TOL * aB + 1e-300)
+
+
+def det_backward(A, B, W, **kw):
+    dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W),
+                          deterministic=True, **kw)
+    torch.cuda.synchronize()
+    return dA.cpu().numpy(), dB.cpu().numpy()
+
+
+def rmat_square_instance(scale, seed):
+    G = synth.rmat_graph(scale, 8, seed=seed)
+    A = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), seed + 3))
+    C, _ = oracle.spgemm(A, A, with_abs=False)
+    W = synth.Csr(C.nrows, C.ncols, C.row_ptr, C.col_idx, synth.normal_values(C.nnz, seed + 4))
+    return A, A, W
+
+
+@pytest.mark.parametrize("case", ["poisson", "rect", "dense_rows", "rmat"])
+def test_deterministic_bitwise_oracle(case):
+    # each entry is one sequential sum in the oracle's order (dA over j
+    # ascending, dB over i ascending), so the bits must agree exactly
+    if case == "poisson":
+        A, B, W = instance(2000, 2000, 2000, 8.0, 8.0, seeds=(8, 9, 10))
+    elif case == "rect":
+        A, B, W = instance(500, 3000, 700, 20.0, 3.0, seeds=(21, 22, 23))
+    elif case == "dense_rows":
+        A, B, W = instance(64, 64, 64, 30.0, 30.0, seeds=(24, 25, 26))
+    else:
+        A, B, W = rmat_square_instance(11, 5)
+    dA, dB = det_backward(A, B, W)
+    rA, rB, aA, aB = oracle.backward(A, B, W)
+    assert np.array_equal(dA, rA)
+    assert np.array_equal(dB, rB)
+    # and repeated calls give the same bits
+    dA2, dB2 = det_backward(A, B, W)
+    assert np.array_equal(dA.view(np.int64), dA2.view(np.int64))
+    assert np.array_equal(dB.view(np.int64), dB2.view(np.int64))
+
+
+def test_deterministic_one_output_and_empty():
+    A, B, W = instance(300, 200, 250, 4.0, 5.0, seeds=(31, 32, 33))
+    rA, rB, _, _ = oracle.backward(A, B, W)
+    dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W),
+                          need_a=False, deterministic=True)
+    assert dA is None and np.array_equal(dB.cpu().numpy(), rB)
+    dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W),
+                          need_b=False, deterministic=True)
+    assert dB is None and np.array_equal(dA.cpu().numpy(), rA)
+    # A with no entries: both gradients are empty / zero
+    Z = synth.Csr(40, 30, np.zeros(41, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    B2 = synth.poisson_csr(30, 20, 3.0, 34)
+    C, _ = oracle.spgemm(Z, B2, with_abs=False)
+    W2 = synth.Csr(C.nrows, C.ncols, C.row_ptr, C.col_idx, np.zeros(C.nnz))
+    dA, dB = det_backward(Z, B2, W2)
+    assert dA.size == 0 and np.all(dB == 0.0)
+
+
+@pytest.mark.parametrize("deterministic", [False, True])
+def test_structure_error_raises(deterministic):
+    # W misses one entry of C's pattern: the adjoint must report it
+    A, B, W = instance(400, 300, 350, 5.0, 5.0, seeds=(41, 42, 43))
+    rp = W.row_ptr.copy()
+    row = int(np.argmax(np.diff(rp)))
+    drop = int(rp[row])
+    ci = np.delete(W.col_idx, drop)
+    v = np.delete(W.values, drop)
+    rp[row + 1:] -= 1
+    W2 = synth.Csr(W.nrows, W.ncols, rp, ci, v)
+    with pytest.raises(mls.SpgemmError, match="STRUCTURE"):
+        mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W2),
+                     deterministic=deterministic)
+    # the flag was cleared: the next call on the same workspace is clean
+    mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W),
+                 deterministic=deterministic)
+
+
+def test_autograd_detects_inplace_change():
+    A = synth.random_csr(30, 20, 0.2, 5)
+    B = synth.random_csr(20, 25, 0.2, 6)
+    dA_, dB_ = mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B)
+    av = dA_.values.clone().requires_grad_(True)
+    bv = dB_.values.clone().requires_grad_(True)
+    C = mls.symbolic(dA_, dB_, with_values=False)
+    a2 = av * 1.0
+    cv = mls.SpGEMMFn.apply(a2, bv, dA_, dB_, C)
+    with torch.no_grad():
+        a2.add_(1.0)   # changes a saved input after the forward pass
+    with pytest.raises(RuntimeError):
+        cv.sum().backward()
+
+
+@pytest.mark.parametrize("cls", [0, 2, 4])
+def test_forced_class_fused(cls):
+    A, B, W = instance(600, 500, 550, 6.0, 7.0, seeds=(51, 52, 53))
+    mls.set_option(mls._abi.OPT_FORCE_CLASS, cls)
+    try:
+        dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W))
+    finally:
+        mls.set_option(mls._abi.OPT_FORCE_CLASS, -1)
+    rA, rB, aA, aB = oracle.backward(A, B, W)
+    assert np.all(np.abs(dA.cpu().numpy() - rA) <= TOL * aA + 1e-300)
+    assert np.all(np.abs(dB.cpu().numpy() - rB) <= TOL * aB + 1e-300)

@@ -78,3 +78,23 @@ def plan_base(A, B, R):
     """Workspace the plan reserves beside the part buffers (budget-independent)."""
     p = mls.chunked_plan(A.row_ptr, B.row_ptr, B.ncols, R.row_ptr, 10**10)
     return p.info["ws_bytes"] - p.info["chunk_bytes"]
+
+
+def test_chunked_after_unsynchronised_product_on_same_workspace():
+    # the chunked call's copy streams must wait for the work still queued on
+    # the compute stream that uses the same workspace
+    A = synth.stencil27_3d(16, amp=0.1, seed=6)
+    ws = mls.Workspace()
+    dA = mls.DeviceCsr.from_host(A)
+    R, _ = oracle.spgemm(A, A)
+    for _ in range(2):
+        C = mls.spgemm(dA, dA, ws)   # numeric phase still running when the next call starts
+        Ah = mls.HostCsr.from_host(A)
+        Ch = mls.HostCsr.from_host(synth.Csr(R.nrows, R.ncols, R.row_ptr, R.col_idx, np.full(R.nnz, np.nan)))
+        plan = mls.chunked_plan(A.row_ptr, A.row_ptr, A.ncols, R.row_ptr, plan_base(A, A, R) + 400_000,
+                                nbuf=2, min_parts=2)
+        assert plan.info["ws_bytes"] <= ws.nbytes
+        mls.numeric_chunked(Ah, Ah, Ch, plan, ws)
+        torch.cuda.synchronize()
+        assert np.array_equal(Ch.values.numpy(), R.values)
+        assert np.array_equal(C.values.cpu().numpy(), R.values)

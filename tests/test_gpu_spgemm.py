@@ -24,6 +24,7 @@ def _reset_options():
     mls.set_option(mls._abi.OPT_GROUP_SIZE, 0)
     mls.set_option(mls._abi.OPT_VALIDATE, 1)
     mls.set_option(mls._abi.OPT_WIDE_TABLE, 0)
+    mls.set_option(mls._abi.OPT_FORCE_CLASS, -1)
 
 
 def gpu_product(A, B):
@@ -396,3 +397,16 @@ def test_device_validation_group_rows(side, length, row, where):
         X, Y = synth.poisson_csr(30, 40, 4.0, 2), Mbad
     with pytest.raises(mls.SpgemmError, match="BAD_CSR"):
         mls.symbolic(mls.DeviceCsr.from_host(X), mls.DeviceCsr.from_host(Y))
+
+
+@pytest.mark.parametrize("cls", [0, 1, 2, 3, 4])
+def test_forced_class(cls):
+    # every row moves up to LDS class `cls` (count, fill and numeric): each
+    # class kernel then sees short rows, long rows and rows with no work
+    mls.set_option(mls._abi.OPT_FORCE_CLASS, cls)
+    check(synth.stencil27_3d(7, amp=0.1), synth.stencil27_3d(7, amp=0.1, seed=3))
+    check(synth.poisson_csr(700, 500, 6.0, 7), synth.poisson_csr(500, 650, 9.0, 8))
+    A = synth.random_csr(200, 150, 0.05, 3, empty_rows=0.5)
+    B = synth.random_csr(150, 120, 0.05, 4, empty_rows=0.5)
+    check(A, B)
+    check(wide_rows(24, 3000, 120, 11), synth.poisson_csr(3000, 9000, 8.0, 12))

@@ -17,6 +17,7 @@ mls = pytest.importorskip("paper_1804_00695_amd")
 def _reset():
     yield
     mls.set_option(mls._abi.OPT_FORCE_SPILL, 0)
+    mls.set_option(mls._abi.OPT_FORCE_CLASS, -1)
 
 
 def gpu_tc(G):
@@ -117,3 +118,13 @@ def test_class_boundaries():
     assert total == ref_total
     assert np.array_equal(counts.cpu().numpy(), ref_counts)
     assert ref_total > 0
+
+
+@pytest.mark.parametrize("cls", [0, 1, 2, 3, 4])
+def test_forced_class(cls):
+    mls.set_option(mls._abi.OPT_FORCE_CLASS, cls)
+    check(synth.rmat_graph(10, 8, seed=7))
+    n = 30
+    e = [(i, j) for i in range(n) for j in range(i + 1, n)]
+    a = np.array(e)
+    assert check(synth.graph_from_edges(n, a[:, 0], a[:, 1])) == comb(n, 3)
