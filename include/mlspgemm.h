@@ -171,6 +171,22 @@ spgemm_status spgemm_numeric(const spgemm_csr *A, const spgemm_csr *B, spgemm_cs
  * the stream). */
 spgemm_status spgemm_check_errors(void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): spgemm_numeric with
+ * no workspace argument. Same kernels, same results bit for bit. Its scratch
+ * is a fixed 64 MiB array in device memory that each GPU the library runs on
+ * holds until the process ends (the per-row arrays take about 17 bytes per
+ * row of A, so A may have up to about 3.9 million rows); a larger A returns
+ * SPGEMM_ERR_WORKSPACE_TOO_SMALL before anything is queued. Allocates no
+ * device memory and makes no host-to-device copy. The caller still owns A, B
+ * and C (device memory, C's structure from the symbolic phase). Every call on
+ * one GPU uses that GPU's same array: calls that overlap in time on one GPU
+ * (two streams, two threads) race and give wrong results; serialise them.
+ * Device-side errors (a column missing from C) are recorded in the array's
+ * first word and are not reported by this call. Does not synchronise. */
+spgemm_status spgemm_numeric_noalloc(const spgemm_csr *A, const spgemm_csr *B, spgemm_csr *C,
+                                     hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Chunked execution between pinned host memory and HBM (Sec. 3.3.1)
  * --------------------------------------------------------------------- */

@@ -229,6 +229,16 @@ def numeric(A: DeviceCsr, B: DeviceCsr, C: DeviceCsr, ws: Optional[Workspace] = 
     return C
 
 
+def numeric_noalloc(A: DeviceCsr, B: DeviceCsr, C: DeviceCsr) -> DeviceCsr:
+    """Numeric phase without a workspace: the library's fixed device scratch
+    array (for callers that cannot allocate). C.values must be allocated."""
+    if C.values is None:
+        raise ValueError("numeric_noalloc writes into C.values, which must be allocated")
+    check(lib.spgemm_numeric_noalloc(ctypes.byref(A.handle()), ctypes.byref(B.handle()), ctypes.byref(C.handle()),
+                                     stream_handle()), "spgemm_numeric_noalloc")
+    return C
+
+
 def check_errors(ws: Optional[Workspace] = None, device="cuda"):
     w = _ws(ws, device)
     check(lib.spgemm_check_errors(w.get(0), w.nbytes, stream_handle()), "spgemm_check_errors")

@@ -53,6 +53,7 @@ SIGNATURES = {
     "spgemm_symbolic": (ctypes.c_int, [CSRP, CSRP, P, P, I64P, P, c_size_t, P]),
     "spgemm_numeric": (ctypes.c_int, [CSRP, CSRP, CSRP, P, c_size_t, P]),
     "spgemm_check_errors": (ctypes.c_int, [P, c_size_t, P]),
+    "spgemm_numeric_noalloc": (ctypes.c_int, [CSRP, CSRP, CSRP, P]),
     "spgemm_chunked_plan": (ctypes.c_int, [CSRP, CSRP, P, c_size_t, c_int32, c_int32, ctypes.POINTER(P)]),
     "spgemm_plan_info_get": (ctypes.c_int, [P, ctypes.POINTER(PlanInfo)]),
     "spgemm_plan_parts": (ctypes.c_int, [P, c_int32, P, c_int32]),

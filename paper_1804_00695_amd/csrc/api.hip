@@ -148,7 +148,7 @@ static bool csr_ok(const spgemm_csr *M, bool need_values)
 // there is more than one product.
 spgemm_status prepare_batch(int32_t nbatch, const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *C,
                             bool need_values, bool need_bw, char *ws, size_t ws_bytes, hipStream_t s,
-                            BatchHost &out)
+                            BatchHost &out, bool upload)
 {
     if (nbatch < 1 || !A || !B) return SPGEMM_ERR_INVALID_ARG;
     int64_t na = 0, nb = 0, zb = 0, maxc = 0, za = 0;
@@ -222,6 +222,7 @@ spgemm_status prepare_batch(int32_t nbatch, const spgemm_csr *A, const spgemm_cs
         key.push_back((uint64_t)B[t].nnz);
         key.push_back(C ? (uint64_t)(uintptr_t)C[t].row_ptr : 0ull);
     }
+    if (!upload) return nbatch == 1 ? SPGEMM_OK : SPGEMM_ERR_INVALID_ARG;
     hipError_t e = hipSuccess;
     e = hipMemcpyAsync(ws + out.layout.nnz_tab, out.nnz_tab.data(), sizeof(int64_t) * out.nnz_tab.size(),
                        hipMemcpyHostToDevice, s);

@@ -63,9 +63,12 @@ Layout make_layout(int64_t nprob, int64_t na, int64_t nb, int64_t zb, int64_t ma
 Sched make_sched(char *ws, const Layout &L);
 void reset_header(char *ws, const Layout &L, hipStream_t s);
 spgemm_status read_errors(char *ws, const Layout &L, hipStream_t s);
+// upload = false skips the host-to-device copies of the descriptor tables
+// (only a single product's numeric phase can do without them: it passes its
+// descriptor by value and never reads the entry-count table).
 spgemm_status prepare_batch(int32_t nbatch, const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *C,
                             bool need_values, bool need_bw, char *ws, size_t ws_bytes, hipStream_t s,
-                            BatchHost &out);
+                            BatchHost &out, bool upload = true);
 spgemm_status run_symbolic(BatchHost &bh, char *ws, int fill, int64_t *nnz_host, hipStream_t s);
 spgemm_status run_numeric(BatchHost &bh, char *ws, hipStream_t s);
 int choose_group(double avg);
