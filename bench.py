@@ -30,8 +30,10 @@ headline product (the same run that the parity check uses).
 The other parts of the metric are measured too (``extras``), unless --quick:
   tc       : triangle counting on R-MAT scale 22 (edge factor 16, seed 3);
   chunked  : the numeric phase with A, B, C in pinned host memory under HBM
-             budgets of 8 GB, 2 GB, 512 MB and 256 MB, pipelined and in the
-             paper's single-buffered mode, end to end including copies;
+             budgets of 8 GB, 2 GB, 512 MB and 256 MB, pipelined (2, 3, 4
+             buffers), in the paper's single-buffered mode, and under
+             Alg. chunkknl (only B copied; A and C used in place, in pinned
+             host memory or in HBM), end to end including copies;
   batched  : 256 Galerkin products Ac = P^T (A P) on 7-point Laplacians
              (n ~ U{16..64}, seed 4): batched two-stage pipeline and numeric
              graph replay against 256 separate calls per stage;
@@ -386,38 +388,54 @@ def headline_oracle(A, madds, rp, ci, v):
 # chunked (pinned host A, B, C; HBM budget)
 
 def bench_chunked(torch, mls, synth, A, host_c, ms_numeric_hbm):
-    """Chunked numeric phase, end to end (copies included), for several budgets,
-    pipelined and in the paper's single-buffered mode; each result compared
-    bit for bit with the in-HBM C."""
+    """Chunked numeric phase, end to end (copies included), for several budgets:
+    Algs. chunk1 / chunk2 pipelined with 2, 3 and 4 inner buffers and in the
+    paper's single-buffered mode, and Alg. chunkknl (only B's parts copied)
+    with A and C in pinned host memory (used in place) or in HBM; each result
+    compared bit for bit with the in-HBM C."""
     C_rp, C_ci, C_v = host_c
     Ah = mls.HostCsr.from_host(A)
     nnzC = len(C_ci)
     Ch = mls.HostCsr(A.nrows, A.ncols, torch.from_numpy(C_rp).pin_memory(),
                      torch.from_numpy(C_ci).pin_memory(), torch.empty(nnzC, dtype=torch.float64).pin_memory())
+    Ad = mls.DeviceCsr.from_host(A)
+    Cd = mls.DeviceCsr(A.nrows, A.ncols, torch.from_numpy(C_rp).cuda(), torch.from_numpy(C_ci).cuda(),
+                       torch.empty(nnzC, dtype=torch.float64, device="cuda"))
     streams = mls.ChunkStreams()
     ws = mls.Workspace()
-    out = {"pcie_peak": pcie_peak(torch)}
-    log(f"pcie peak: {out['pcie_peak']}")
+    peak = pcie_peak(torch)
+    out = {"pcie_peak": peak}
+    log(f"pcie peak: {peak}")
     ok = True
+    modes = (("pipelined", 2, 4, None), ("nbuf3", 3, 4, None), ("nbuf4", 4, 4, None), ("paper", 1, 1, None),
+             ("knl_AC_pinned", 2, 2, "pinned"), ("knl_AC_hbm", 2, 2, "hbm"))
     for label, budget in (("8GB", 8 << 30), ("2GB", 2 << 30), ("512MB", 512 << 20), ("256MB", 256 << 20)):
-        for mode, nbuf, min_parts in (("pipelined", 2, 4), ("paper", 1, 1)):
-            plan = mls.chunked_plan(A.row_ptr, A.row_ptr, A.ncols, C_rp, budget, nbuf=nbuf, min_parts=min_parts)
-            Ch.values.fill_(float("nan"))
-            med, best = timed(torch, lambda: mls.numeric_chunked(Ah, Ah, Ch, plan, ws, streams), 3)
+        for mode, nbuf, min_parts, knl in modes:
+            plan = mls.chunked_plan(A.row_ptr, A.row_ptr, A.ncols, C_rp, budget, nbuf=nbuf, min_parts=min_parts,
+                                    knl=knl is not None)
+            a, c = (Ad, Cd) if knl == "hbm" else (Ah, Ch)
+            c.values.fill_(float("nan"))
+            med, best = timed(torch, lambda: mls.numeric_chunked(a, Ah, c, plan, ws, streams), 3)
             info = plan.info   # after a run: holds the bytes the last run issued
             moved = info["issued_h2d"] + info["issued_d2h"]
-            bit = same_bits(Ch.values.numpy(), C_v)
+            got = c.values.cpu().numpy() if knl == "hbm" else c.values.numpy()
+            bit = same_bits(got, C_v)
             ok = ok and bit
-            key = label if mode == "pipelined" else f"{label}_paper_mode"
+            key = label if mode == "pipelined" else f"{label}_{mode}"
             out[key] = {"ms": round(med, 2), "best_ms": round(best, 2),
                         "slowdown_vs_hbm": round(med / ms_numeric_hbm, 2), "mode": mode, "nbuf": nbuf,
-                        "min_parts": min_parts, "algo": f"chunk{info['algo']}", "branch": info["branch"],
-                        "parts_ac": info["n_ac_parts"], "parts_b": info["n_b_parts"],
+                        "min_parts": min_parts, "algo": {1: "chunk1", 2: "chunk2", 3: "chunkknl"}[info["algo"]],
+                        "branch": info["branch"], "parts_ac": info["n_ac_parts"], "parts_b": info["n_b_parts"],
                         "h2d_GB": round(info["h2d_bytes"] / 1e9, 3), "d2h_GB": round(info["d2h_bytes"] / 1e9, 3),
                         "issued_equals_plan": info["issued_h2d"] == info["h2d_bytes"] and
                         info["issued_d2h"] == info["d2h_bytes"],
-                        "pcie_GBs": round(moved / (med * 1e-3) / 1e9, 1), "bitwise_vs_in_hbm": bit}
+                        "pcie_GBs": round(moved / (med * 1e-3) / 1e9, 1),
+                        "link_frac_of_duplex_peak": round(moved / (med * 1e-3) / 1e9 / peak["duplex_GBs"], 3),
+                        "bitwise_vs_in_hbm": bit}
+            if knl == "pinned":
+                out[key]["zero_copy_GB"] = round(info["zero_copy_bytes"] / 1e9, 3)
             log(f"chunked {key}: {out[key]}")
+            del plan
     return out, ok
 
 
@@ -653,6 +671,239 @@ def bench_power_law(torch, mls, synth, with_parity):
 
 
 # ---------------------------------------------------------------------------
+# multigrid stand-ins: data placement (Table "gpudp") and chunk sweeps
+
+MG_NAMES = ("laplace3d", "bigstar2d", "brick3d", "elasticity3d")
+PLACEMENTS = (("A_Pin", (1, 0, 0)), ("B_Pin", (0, 1, 0)), ("C_Pin", (0, 0, 1)), ("HostPin", (1, 1, 1)))
+
+
+def mg_build(mls, name, gb):
+    """(grid edge, A, P, R) of a multigrid stand-in with A of about `gb` GB,
+    generated on the GPU (positional values: the same matrix on any device)."""
+    from synth import multigrid as mg
+    n = mg.grid_for_bytes(name, gb * 1e9)
+    A, P, R = mg.problem(name, n, device="cuda")
+    dev = lambda M: mls.DeviceCsr(M.nrows, M.ncols, M.row_ptr, M.col_idx, M.values)
+    return n, dev(A), dev(P), dev(R)
+
+
+def pinned_copy(torch, mls, D, values=True):
+    def pin(t):
+        h = torch.empty(t.numel(), dtype=t.dtype, pin_memory=True)
+        h.copy_(t)
+        return h
+    v = pin(D.values) if (values and D.values is not None) else None
+    return mls.HostCsr(D.nrows, D.ncols, pin(D.row_ptr), pin(D.col_idx), v)
+
+
+def host_cache_release(torch):
+    """Hand the pinned blocks torch caches back to the system."""
+    fn = getattr(torch._C, "_host_emptyCache", None)
+    if fn is not None:
+        fn()
+
+
+def dcsr_bytes(M):
+    return csr_bytes(M.nrows, M.nnz)
+
+
+def host_numpy(M):
+    import synth
+    v = None if M.values is None else M.values.cpu().numpy()
+    return synth.Csr(M.nrows, M.ncols, M.row_ptr.cpu().numpy(), M.col_idx.cpu().numpy(), v)
+
+
+def bench_placement(torch, mls, gb, with_parity, names=MG_NAMES):
+    """Table "gpudp" on MI355X: the numeric phase of R x A and A x P with all of
+    A, B, C in HBM, then with one of them (or all three) in pinned host memory
+    read and written in place by the kernels. Every placement's C is compared
+    bit for bit with the all-in-HBM C, and that one with the oracle."""
+    ws = mls.Workspace()
+    flush = Flush(torch)
+    rows, ok = [], True
+    for name in names:
+        log(f"placement: {name} ({gb} GB A)")
+        n, A, P, R = mg_build(mls, name, gb)
+        for prod, (L, Rt) in (("RxA", (R, A)), ("AxP", (A, P))):
+            C = mls.symbolic(L, Rt, ws)
+            _, madds = mls.row_work(L, Rt, ws)
+            hbm = lambda: mls.numeric(L, Rt, C, ws)
+            hbm()
+            t_hbm, b_hbm = timed(torch, hbm, 5, pre=flush)
+            ref = C.values.cpu().numpy()
+            gfl = lambda ms: round(2.0 * madds / (ms * 1e-3) / 1e9, 2)
+            entry = {"problem": name, "product": prod, "grid": n, "multiply_adds": int(madds),
+                     "GB": {"A": round(dcsr_bytes(L) / 1e9, 3), "B": round(dcsr_bytes(Rt) / 1e9, 3),
+                            "C": round(dcsr_bytes(C) / 1e9, 3)},
+                     "GFLOPs": {"HBM": gfl(t_hbm)}, "ms": {"HBM": round(t_hbm, 3)}, "bitwise_vs_HBM": {}}
+            hL, hR = pinned_copy(torch, mls, L), pinned_copy(torch, mls, Rt)
+            hC = pinned_copy(torch, mls, C)
+            for label, (pa, pb, pc) in PLACEMENTS:
+                a, b = (hL if pa else L), (hR if pb else Rt)
+                c = hC if pc else C
+                c.values.fill_(float("nan"))
+                fn = lambda: mls.numeric_placed(a, b, c, ws)
+                fn()
+                t, _ = timed(torch, fn, 2, pre=flush)
+                got = c.values.numpy() if pc else c.values.cpu().numpy()
+                bit = same_bits(got, ref)
+                ok = ok and bit
+                entry["GFLOPs"][label] = gfl(t)
+                entry["ms"][label] = round(t, 3)
+                entry["bitwise_vs_HBM"][label] = bit
+            entry["slowdown_vs_HBM"] = {k: round(entry["ms"][k] / entry["ms"]["HBM"], 2) for k, _ in PLACEMENTS}
+            if with_parity:
+                import oracle
+                Rf, _ = oracle.spgemm(host_numpy(L), host_numpy(Rt), nthreads=oracle_threads(), with_abs=False)
+                rp, ci = C.row_ptr.cpu().numpy(), C.col_idx.cpu().numpy()
+                par = same_bits(rp, Rf.row_ptr) and same_bits(ci, Rf.col_idx) and same_bits(ref, Rf.values)
+                entry["oracle_bitwise"] = par
+                ok = ok and par
+            log(f"placement {name} {prod}: {entry}")
+            rows.append(entry)
+            del hL, hR, hC, C
+        del A, P, R
+        torch.cuda.empty_cache()
+        host_cache_release(torch)
+    return {"gb_of_A": gb, "products": rows}, ok
+
+
+def bench_mg_sweep(torch, mls, sizes, budgets_gb=(8, 16), names=MG_NAMES, hostpin_max_gb=4.0, reps=2):
+    """Figs. "expgpuap" / "expgpura" on MI355X: R x A and A x P on the four
+    stand-ins as A grows, all in HBM, all in pinned host memory (zero copy,
+    up to hostpin_max_gb), and chunked under HBM budgets of 8 and 16 GB
+    (Chunk8, Chunk16; pipelined plan executed, the paper-mode plan reported
+    beside it). Every chunked C is compared bit for bit with the in-HBM C."""
+    ws = mls.Workspace()
+    streams = mls.ChunkStreams()
+    flush = Flush(torch)
+    rows, ok = [], True
+    for name in names:
+        for gb in sizes:
+            log(f"sweep: {name} {gb} GB")
+            n, A, P, R = mg_build(mls, name, gb)
+            for prod, (L, Rt) in (("RxA", (R, A)), ("AxP", (A, P))):
+                C = mls.symbolic(L, Rt, ws)
+                _, madds = mls.row_work(L, Rt, ws)
+                hbm = lambda: mls.numeric(L, Rt, C, ws)
+                hbm()
+                t_hbm, _ = timed(torch, hbm, 3, pre=flush)
+                ref = C.values.cpu().numpy()
+                gfl = lambda ms: round(2.0 * madds / (ms * 1e-3) / 1e9, 2)
+                sA, sB, sC = dcsr_bytes(L), dcsr_bytes(Rt), dcsr_bytes(C)
+                entry = {"problem": name, "product": prod, "gb_of_A_target": gb, "grid": n,
+                         "GB": {"A": round(sA / 1e9, 3), "B": round(sB / 1e9, 3), "C": round(sC / 1e9, 3)},
+                         "multiply_adds": int(madds), "HBM": {"ms": round(t_hbm, 3), "GFLOPs": gfl(t_hbm)}}
+                hL, hR, hC = (pinned_copy(torch, mls, M) for M in (L, Rt, C))
+                arp, brp, crp = (M.row_ptr.numpy() for M in (hL, hR, hC))
+                if gb <= hostpin_max_gb:
+                    hC.values.fill_(float("nan"))
+                    fn = lambda: mls.numeric_placed(hL, hR, hC, ws)
+                    t_pin, _ = timed(torch, fn, 1, pre=flush)
+                    bit = same_bits(hC.values.numpy(), ref)
+                    ok = ok and bit
+                    entry["HostPin"] = {"ms": round(t_pin, 2), "GFLOPs": gfl(t_pin), "bitwise_vs_HBM": bit}
+                for bgb in budgets_gb:
+                    budget = int(bgb) << 30
+                    key = f"Chunk{bgb}"
+                    try:
+                        paper = mls.chunked_plan(arp, brp, Rt.ncols, crp, budget, nbuf=1, min_parts=1).info
+                        plan = mls.chunked_plan(arp, brp, Rt.ncols, crp, budget, nbuf=2, min_parts=4)
+                    except mls.SpgemmError as e:
+                        entry[key] = {"error": str(e)}
+                        continue
+                    hC.values.fill_(float("nan"))
+                    fn = lambda: mls.numeric_chunked(hL, hR, hC, plan, ws, streams)
+                    t, best = timed(torch, fn, reps)
+                    info = plan.info
+                    bit = same_bits(hC.values.numpy(), ref)
+                    ok = ok and bit
+                    moved = info["issued_h2d"] + info["issued_d2h"]
+                    # A, B and C's structure in once, C's values out once (plus the
+                    # duplicated boundary row pointer of each part)
+                    compulsory = sA + sB + sC
+                    res = {"ms": round(t, 2), "best_ms": round(best, 2), "GFLOPs": gfl(t),
+                           "slowdown_vs_HBM": round(t / t_hbm, 2), "algo": f"chunk{info['algo']}",
+                           "branch": info["branch"], "parts_ac": info["n_ac_parts"], "parts_b": info["n_b_parts"],
+                           "copied_GB": round(moved / 1e9, 3), "link_GBs": round(moved / (t * 1e-3) / 1e9, 1),
+                           "bitwise_vs_HBM": bit,
+                           "paper_mode_plan": {"algo": f"chunk{paper['algo']}", "branch": paper["branch"],
+                                               "parts_ac": paper["n_ac_parts"], "parts_b": paper["n_b_parts"],
+                                               "copied_GB": round((paper["h2d_bytes"] + paper["d2h_bytes"]) / 1e9, 3),
+                                               "optimal_copy": paper["h2d_bytes"] + paper["d2h_bytes"] - compulsory
+                                               <= 8 * (paper["n_ac_parts"] + paper["n_b_parts"]),
+                                               "whole_problem_fits": paper["n_ac_parts"] == 1 and paper["n_b_parts"] == 1}}
+                    if "HostPin" in entry:
+                        res["speedup_vs_HostPin"] = round(entry["HostPin"]["ms"] / t, 2)
+                    entry[key] = res
+                    del plan
+                log(f"sweep {name} {gb} {prod}: {entry}")
+                rows.append(entry)
+                del hL, hR, hC, C
+                host_cache_release(torch)
+            del A, P, R
+            torch.cuda.empty_cache()
+            host_cache_release(torch)
+    return {"sizes_gb": list(sizes), "budgets_gb": list(budgets_gb), "runs": rows}, ok
+
+
+def bench_density(torch, mls, with_parity, n=24, deltas=(1, 4, 16, 64, 256)):
+    """Table "expdensity" on MI355X: the elasticity stand-in's R and A times a
+    random right-hand side with delta entries per row (as many columns as P),
+    numeric phase with everything in HBM, with the right-hand side in pinned
+    host memory (B_Pin, read in place), and with all three in pinned host
+    memory (HostPin, the analog of the paper's all-in-DDR runs). Every
+    placement's C is compared bit for bit with the in-HBM C, and that one with
+    the oracle."""
+    from synth import multigrid as mg
+    ws = mls.Workspace()
+    flush = Flush(torch)
+    A, P, R = mg.problem("elasticity3d", n, device="cuda")
+    dev = lambda M: mls.DeviceCsr(M.nrows, M.ncols, M.row_ptr, M.col_idx, M.values)
+    A, R = dev(A), dev(R)
+    rows, ok = [], True
+    for delta in deltas:
+        rhs = dev(mg.random_rhs(A.ncols, P.ncols, delta, seed=100 + delta, device="cuda"))
+        for name, L in (("R x RHS", R), ("A x RHS", A)):
+            C = mls.symbolic(L, rhs, ws)
+            _, madds = mls.row_work(L, rhs, ws)
+            hbm = lambda: mls.numeric(L, rhs, C, ws)
+            hbm()
+            t_hbm, _ = timed(torch, hbm, 5, pre=flush)
+            ref = C.values.cpu().numpy()
+            gfl = lambda ms: round(2.0 * madds / (ms * 1e-3) / 1e9, 2)
+            hL, hB, hC = (pinned_copy(torch, mls, M) for M in (L, rhs, C))
+            entry = {"product": name, "delta": delta, "multiply_adds": int(madds), "nnz_C": int(C.nnz),
+                     "GFLOPs": {"HBM": gfl(t_hbm)}, "ms": {"HBM": round(t_hbm, 3)}, "bitwise_vs_HBM": {}}
+            for label, (a, b, c) in (("B_Pin", (L, hB, C)), ("HostPin", (hL, hB, hC))):
+                c.values.fill_(float("nan"))
+                fn = lambda: mls.numeric_placed(a, b, c, ws)
+                fn()
+                t, _ = timed(torch, fn, 3, pre=flush)
+                got = c.values.numpy() if c is hC else c.values.cpu().numpy()
+                bit = same_bits(got, ref)
+                ok = ok and bit
+                entry["GFLOPs"][label] = gfl(t)
+                entry["ms"][label] = round(t, 3)
+                entry["bitwise_vs_HBM"][label] = bit
+            if with_parity:
+                import oracle
+                Rf, _ = oracle.spgemm(host_numpy(L), host_numpy(rhs), nthreads=oracle_threads(), with_abs=False)
+                par = same_bits(C.row_ptr.cpu().numpy(), Rf.row_ptr) and \
+                    same_bits(C.col_idx.cpu().numpy(), Rf.col_idx) and same_bits(ref, Rf.values)
+                entry["oracle_bitwise"] = par
+                ok = ok and par
+            log(f"density {name} delta={delta}: {entry}")
+            rows.append(entry)
+            del hL, hB, hC, C
+        del rhs
+        torch.cuda.empty_cache()
+        host_cache_release(torch)
+    return {"problem": f"elasticity3d on {n}^3 nodes ({A.nrows} rows), RHS {A.ncols} x {P.ncols}",
+            "products": rows}, ok
+
+
+# ---------------------------------------------------------------------------
 # triangle counting
 
 def tc_word_model(n, lrp, lci):
@@ -730,7 +981,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only: no extras, no parity, no CPU baseline")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle comparisons")
     ap.add_argument("--workload", default="all",
-                    choices=["all", "spgemm", "tc", "chunked", "batched", "backward", "power_law"])
+                    choices=["all", "spgemm", "tc", "chunked", "batched", "backward", "power_law", "placement",
+                             "mg_sweep", "density"])
+    ap.add_argument("--mg-gb", type=float, default=1.0, help="size of A (GB) in the placement study")
+    ap.add_argument("--mg-sizes", default="1,2,4,8,16", help="sizes of A (GB) in the multigrid chunk sweep")
+    ap.add_argument("--mg-problems", default=",".join(MG_NAMES))
+    ap.add_argument("--hostpin-max-gb", type=float, default=4.0)
     ap.add_argument("--tc-scale", type=int, default=22)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (anchors HBM byte counters)")
@@ -755,7 +1011,13 @@ def main():
     single = {"tc": lambda: bench_tc(torch, mls, synth, args.tc_scale, parity),
               "batched": lambda: bench_batched(torch, mls, synth, parity),
               "backward": lambda: bench_backward(torch, mls, synth, parity),
-              "power_law": lambda: bench_power_law(torch, mls, synth, parity)}
+              "power_law": lambda: bench_power_law(torch, mls, synth, parity),
+              "placement": lambda: bench_placement(torch, mls, args.mg_gb, parity,
+                                                   tuple(args.mg_problems.split(","))),
+              "density": lambda: bench_density(torch, mls, parity),
+              "mg_sweep": lambda: bench_mg_sweep(torch, mls, [float(x) for x in args.mg_sizes.split(",")],
+                                                 names=tuple(args.mg_problems.split(",")),
+                                                 hostpin_max_gb=args.hostpin_max_gb)}
     if args.workload in single:
         res, ok = single[args.workload]()
         res["parity_ok"] = ok

@@ -166,6 +166,21 @@ spgemm_status spgemm_symbolic(const spgemm_csr *A, const spgemm_csr *B, int32_t 
 spgemm_status spgemm_numeric(const spgemm_csr *A, const spgemm_csr *B, spgemm_csr *C,
                              void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Data placement (Sec. 3.3, Table "gpudp"): spgemm_numeric with any of A, B
+ * and C left in page-locked host memory, read (A, B, C's structure) and
+ * written (C's values) in place by the kernels over the host link, with no
+ * copy -- the paper's A_Pin, B_Pin, C_Pin and HostPin placements. Each array
+ * pointer must be device memory of the current device or host memory
+ * allocated page-locked with hipHostMalloc (torch's pin_memory), which is
+ * used through its device mapping; pageable host memory, managed memory and
+ * memory of another device give SPGEMM_ERR_INVALID_ARG before anything is
+ * queued. The workspace must be device memory of the current device (same
+ * size as for spgemm_numeric). *placement_out (may be NULL) receives bit 0,
+ * 1, 2 set when an array of A, B, C is in host memory. Same kernels and the
+ * same results, bit for bit, as spgemm_numeric. Does not synchronise. */
+spgemm_status spgemm_numeric_placed(const spgemm_csr *A, const spgemm_csr *B, spgemm_csr *C,
+                                    uint32_t *placement_out, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Reports and clears the device-side error flag of a workspace (the word at
  * its start) after the work queued on the stream has finished (synchronises
  * the stream). */
@@ -195,11 +210,13 @@ typedef struct spgemm_plan spgemm_plan;
 
 typedef struct {
     int32_t algo;            /* 1 = Alg. chunk1 (A/C parts in place, B streams),
-                                2 = Alg. chunk2 (B parts in place, A/C stream) */
-    int32_t branch;          /* which case of Alg. chunker decided (1..4) */
+                                2 = Alg. chunk2 (B parts in place, A/C stream),
+                                3 = Alg. chunkknl (B streams; A and C stay in host
+                                    memory and the kernels access them in place) */
+    int32_t branch;          /* which case of Alg. chunker decided (1..4; 0 for chunkknl) */
     int32_t n_ac_parts;      /* |P_AC| */
     int32_t n_b_parts;       /* |P_B| */
-    int32_t nbuf_inner;      /* buffers of the inner-loop matrix (1 or 2) */
+    int32_t nbuf_inner;      /* buffers of the inner-loop matrix (1 to 4) */
     int32_t n_steps;
     int64_t fast_bytes;      /* FastSize handed to the partition heuristic */
     int64_t h2d_bytes;       /* bytes the schedule copies host -> device */
@@ -210,6 +227,9 @@ typedef struct {
     int64_t ws_bytes;        /* workspace spgemm_numeric_chunked needs (<= budget) */
     int64_t issued_h2d;      /* bytes the last execution actually queued host -> device */
     int64_t issued_d2h;      /* bytes the last execution actually queued device -> host */
+    int64_t zero_copy_bytes; /* chunkknl: bytes the kernels read and write in place in host
+                                memory (A and C's structure read and C's values written by
+                                every pass, C's values read by every pass after the first) */
 } spgemm_plan_info;
 
 /* One step of the schedule, in issue order. */
@@ -228,14 +248,28 @@ typedef struct {
  * pointer of C (host). The HBM budget bounds the workspace that
  * spgemm_numeric_chunked will need; FastSize is the budget less a reserve
  * for the kernels' own per-row arrays. nbuf = 1 reproduces the paper's
- * single-buffered loops; nbuf = 2 double-buffers the inner-loop matrix so
- * its copies overlap the kernel. min_parts >= 1 cuts the inner-loop matrix
- * into at least that many parts (pipelining when it fits whole). Host only,
- * no GPU needed. Errors: SPGEMM_ERR_BUDGET when a single row does not fit
- * its portion. The plan is owned by the caller (spgemm_plan_destroy). */
+ * single-buffered loops; nbuf = 2..4 gives the inner-loop matrix that many
+ * buffers so its copies overlap the kernels (double, triple, quadruple
+ * buffering; the paper names these as future work, Sec. 4.2). min_parts >= 1
+ * cuts the inner-loop matrix into at least that many parts (pipelining when
+ * it fits whole). Host only, no GPU needed. Errors: SPGEMM_ERR_BUDGET when a
+ * single row does not fit its portion. The plan is owned by the caller
+ * (spgemm_plan_destroy). */
 spgemm_status spgemm_chunked_plan(const spgemm_csr *A_host, const spgemm_csr *B_host,
                                   const int32_t *C_row_ptr_host, size_t hbm_budget_bytes,
                                   int32_t nbuf, int32_t min_parts, spgemm_plan **plan_out);
+/* Alg. "chunkknl" (Sec. 3.2.2): only B is partitioned. The number of parts is
+ * ceil(size(B) / portion) (at least min_parts), the balanced part size is
+ * size(B) over that number, and BinarySearch cuts B's rows into parts of at
+ * most that size; portion = FastSize / nbuf. A and C are not copied: the
+ * row-range kernels read A and C's structure and accumulate C's values in
+ * place, over the host link when they are in host memory (with everything
+ * but B in host memory this is the paper's KNL scheme; with B whole in HBM,
+ * its data-placement method). Same arguments and errors as
+ * spgemm_chunked_plan; the plan reports algo = 3. */
+spgemm_status spgemm_chunked_plan_knl(const spgemm_csr *A_host, const spgemm_csr *B_host,
+                                      const int32_t *C_row_ptr_host, size_t hbm_budget_bytes,
+                                      int32_t nbuf, int32_t min_parts, spgemm_plan **plan_out);
 spgemm_status spgemm_plan_info_get(const spgemm_plan *plan, spgemm_plan_info *out);
 /* Copies min(max_parts, n) (begin, end) pairs of P_AC (which = 0) or P_B
  * (which = 1) into ranges[2*i], ranges[2*i+1]. */
@@ -247,11 +281,16 @@ void spgemm_plan_destroy(spgemm_plan *plan);
  * multiply-add kernel, C_r += A_r[:, P_B] * B_b, Sec. 3.2.2/3.3.1). A_host,
  * B_host and C_host hold host pointers to pinned memory (row_ptr, col_idx,
  * values); C_host's structure is the symbolic result and its values are
- * written. ws must hold info.ws_bytes of device memory. Copies host->device
- * are queued on s_h2d, device->host on s_d2h, kernels on s_compute (they
- * may be the same stream); events order them. Synchronises all three
- * streams before returning and records the issued byte counts in the plan.
- * The result equals spgemm_numeric's bit for bit. */
+ * written. For a chunkknl plan (algo 3) A and C are used in place: each of
+ * their arrays must be page-locked host memory from hipHostMalloc (torch's
+ * pin_memory) or device memory of the current device (else
+ * SPGEMM_ERR_INVALID_ARG before anything is queued). ws must hold
+ * info.ws_bytes of device memory. Copies host->device are queued on s_h2d,
+ * device->host on s_d2h, kernels on s_compute (they may be the same stream);
+ * events order them. The row binning of an A/C part is done by its first
+ * kernel step and reused by the others. Synchronises all three streams
+ * before returning and records the issued byte counts in the plan. The
+ * result equals spgemm_numeric's bit for bit. */
 spgemm_status spgemm_numeric_chunked(const spgemm_csr *A_host, const spgemm_csr *B_host,
                                      spgemm_csr *C_host, spgemm_plan *plan, void *ws, size_t ws_bytes,
                                      hipStream_t s_compute, hipStream_t s_h2d, hipStream_t s_d2h);

@@ -1,8 +1,10 @@
 """Oracle for the chunking decision and copy schedule -- TEST INFRASTRUCTURE ONLY.
 
 Follows Sec. 3.3.1 of the paper (Alg. "chunker", the "Partition" heuristic;
-Algs. "chunk1" = AC in place and "chunk2" = B in place), in plain Python, in
-the paper's order. Readings taken where the text is silent or garbled:
+Algs. "chunk1" = AC in place and "chunk2" = B in place) and Sec. 3.2.2
+(Alg. "chunkknl": only B is partitioned, A and C stay in slow memory), in
+plain Python, in the paper's order. Readings taken where the text is silent
+or garbled:
 
 * size of a row range [r0, r1) of a CSR matrix X = 4*(r1 - r0 + 1) bytes of
   row pointers + 12 bytes per stored entry (int32 index + fp64 value).
@@ -39,7 +41,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-CHUNK1, CHUNK2 = 1, 2          # AC in place / B in place
+CHUNK1, CHUNK2, CHUNKKNL = 1, 2, 3   # AC in place / B in place / only B moves
 H2D, D2H, KERNEL, ZERO = 0, 1, 2, 3
 MAT_A, MAT_B, MAT_CSTRUCT, MAT_CVAL = 0, 1, 2, 3
 
@@ -105,6 +107,7 @@ class Plan:
     cost2: int = 0
     ws_chunks: int = 0
     steps: list = field(default_factory=list)
+    zero_copy: int = 0       # chunkknl: bytes the kernels move in place in slow memory
 
 
 def _sizes(arp, brp, crp):
@@ -230,3 +233,34 @@ def schedule(plan: Plan, arp, brp, crp):
                 steps.append((D2H, MAT_CVAL, r, r0, r1, cv, slot))
                 it += 1
     return steps
+
+
+def partition_knl(arp, brp, crp, fast: int, nbuf: int = 1, min_parts: int = 1) -> Plan:
+    """Alg. "chunkknl": np = ceil(size(B) / FastSize) parts of balanced size
+    size(B) / np, cut by BinarySearch; A and C are not copied (the kernels use
+    them in slow memory). With nbuf buffers the portion of a part is
+    FastSize / nbuf; min_parts cuts at least that many parts."""
+    arp = np.asarray(arp, dtype=np.int64)
+    brp = np.asarray(brp, dtype=np.int64)
+    crp = np.asarray(crp, dtype=np.int64)
+    nA, nB, sA, sB, sC = _sizes(arp, brp, crp)
+    max_row_b = int((8 + 12 * np.diff(brp)).max()) if nB else 0
+
+    def size_b(r0, r1):
+        return range_bytes(brp, r0, r1)
+
+    p_b = binary_search(size_b, nB, balanced(sB, fast // nbuf, max_row_b, min_parts))
+    plan = Plan(CHUNKKNL, 0, fast, [(0, nA)], p_b, nbuf)
+    plan.h2d = sum(size_b(b0, b1) for b0, b1 in p_b)
+    plan.d2h = 0
+    plan.ws_chunks = nbuf * max(size_b(b0, b1) for b0, b1 in p_b)
+    nparts = len(p_b)
+    cval = 8 * (int(crp[-1]) - int(crp[0]))
+    # every pass reads A and C's structure where they are and writes C's
+    # values; the passes after the first read the previous values back
+    plan.zero_copy = nparts * (sA + struct_bytes(crp, 0, nA)) + nparts * cval + (nparts - 1) * cval
+    plan.steps = []
+    for q, (b0, b1) in enumerate(p_b):
+        plan.steps.append((H2D, MAT_B, q, b0, b1, size_b(b0, b1), q % nbuf))
+        plan.steps.append((KERNEL, MAT_CVAL, 0, b0, b1, 0, q % nbuf))
+    return plan

@@ -229,6 +229,26 @@ def numeric(A: DeviceCsr, B: DeviceCsr, C: DeviceCsr, ws: Optional[Workspace] = 
     return C
 
 
+def numeric_placed(A, B, C, ws: Optional[Workspace] = None, device="cuda") -> int:
+    """Numeric phase with each of A, B, C either a DeviceCsr (HBM) or a HostCsr
+    (pinned host memory read and written in place by the kernels, no copy).
+    C.values must be allocated where C lives. Returns the placement bits the
+    library found (1 = A, 2 = B, 4 = C in host memory)."""
+    if C.values is None:
+        raise ValueError("numeric_placed writes into C.values, which must be allocated")
+    if A.values is None or B.values is None:
+        raise ValueError("numeric_placed needs the values of A and B")
+    w = _ws(ws, device)
+    sizes = ctypes.c_size_t(0)
+    ha, hb, hc = A.handle(), B.handle(), C.handle()
+    # the workspace depends on shapes and entry counts only
+    check(lib.spgemm_workspace_size(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(sizes)), "spgemm_workspace_size")
+    bits = ctypes.c_uint32(0)
+    check(lib.spgemm_numeric_placed(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(hc), ctypes.byref(bits),
+                                    w.get(sizes.value), sizes.value, stream_handle()), "spgemm_numeric_placed")
+    return bits.value
+
+
 def numeric_noalloc(A: DeviceCsr, B: DeviceCsr, C: DeviceCsr) -> DeviceCsr:
     """Numeric phase without a workspace: the library's fixed device scratch
     array (for callers that cannot allocate). C.values must be allocated."""
@@ -286,8 +306,9 @@ class Plan:
 
 
 def chunked_plan(a_row_ptr, b_row_ptr, ncols_b: int, c_row_ptr, budget: int, nbuf: int = 2,
-                 min_parts: int = 1) -> Plan:
-    """Partition A/C and B into row parts for an HBM budget (host only, no GPU)."""
+                 min_parts: int = 1, knl: bool = False) -> Plan:
+    """Partition A/C and B into row parts for an HBM budget (host only, no GPU).
+    knl=True: Alg. "chunkknl" (only B is cut; A and C are used in place)."""
     arp = np.ascontiguousarray(a_row_ptr, dtype=np.int32)
     brp = np.ascontiguousarray(b_row_ptr, dtype=np.int32)
     crp = np.ascontiguousarray(c_row_ptr, dtype=np.int32)
@@ -295,8 +316,9 @@ def chunked_plan(a_row_ptr, b_row_ptr, ncols_b: int, c_row_ptr, budget: int, nbu
     ha = CsrT(nA, nB, int(arp[-1]), arp.ctypes.data, None, None)
     hb = CsrT(nB, ncols_b, int(brp[-1]), brp.ctypes.data, None, None)
     out = ctypes.c_void_p(0)
-    check(lib.spgemm_chunked_plan(ctypes.byref(ha), ctypes.byref(hb), crp.ctypes.data, int(budget), nbuf, min_parts,
-                                  ctypes.byref(out)), "spgemm_chunked_plan")
+    fn = lib.spgemm_chunked_plan_knl if knl else lib.spgemm_chunked_plan
+    check(fn(ctypes.byref(ha), ctypes.byref(hb), crp.ctypes.data, int(budget), nbuf, min_parts, ctypes.byref(out)),
+          "spgemm_chunked_plan_knl" if knl else "spgemm_chunked_plan")
     return Plan(out.value, (arp, brp, crp))
 
 
@@ -309,12 +331,19 @@ class ChunkStreams:
         self.d2h = torch.cuda.Stream(device)
 
 
-def numeric_chunked(A: HostCsr, B: HostCsr, C: HostCsr, plan: Plan, ws: Optional[Workspace] = None,
-                    streams: Optional[ChunkStreams] = None, device="cuda") -> HostCsr:
-    """Chunked numeric phase: C.values (pinned host) = A*B on C's structure."""
+def numeric_chunked(A, B, C, plan: Plan, ws: Optional[Workspace] = None,
+                    streams: Optional[ChunkStreams] = None, device="cuda"):
+    """Chunked numeric phase: C.values = A*B on C's structure. B (and, for
+    Algs. chunk1 / chunk2, A and C) must be HostCsr in pinned host memory;
+    under a chunkknl plan A and C are used in place and may be HostCsr or
+    DeviceCsr."""
     w = _ws(ws, device)
     nb = plan.info["ws_bytes"]
     st = streams or ChunkStreams(device)
+    if not isinstance(B, HostCsr):
+        raise ValueError("B must be a HostCsr (pinned host memory)")
+    if plan.info["algo"] != 3 and not (isinstance(A, HostCsr) and isinstance(C, HostCsr)):
+        raise ValueError("Algs. chunk1 / chunk2 copy A and C from pinned host memory: pass HostCsr")
     check(lib.spgemm_numeric_chunked(ctypes.byref(A.handle()), ctypes.byref(B.handle()), ctypes.byref(C.handle()),
                                      plan._h, w.get(nb), nb, st.compute.cuda_stream, st.h2d.cuda_stream,
                                      st.d2h.cuda_stream), "spgemm_numeric_chunked")

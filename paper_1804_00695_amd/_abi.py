@@ -21,7 +21,7 @@ class PlanInfo(ctypes.Structure):
                 ("nbuf_inner", c_int32), ("n_steps", c_int32), ("fast_bytes", c_int64),
                 ("h2d_bytes", c_int64), ("d2h_bytes", c_int64), ("cost_chunk1", c_int64),
                 ("cost_chunk2", c_int64), ("chunk_bytes", c_int64), ("ws_bytes", c_int64),
-                ("issued_h2d", c_int64), ("issued_d2h", c_int64)]
+                ("issued_h2d", c_int64), ("issued_d2h", c_int64), ("zero_copy_bytes", c_int64)]
 
 
 class PlanStep(ctypes.Structure):
@@ -54,7 +54,9 @@ SIGNATURES = {
     "spgemm_numeric": (ctypes.c_int, [CSRP, CSRP, CSRP, P, c_size_t, P]),
     "spgemm_check_errors": (ctypes.c_int, [P, c_size_t, P]),
     "spgemm_numeric_noalloc": (ctypes.c_int, [CSRP, CSRP, CSRP, P]),
+    "spgemm_numeric_placed": (ctypes.c_int, [CSRP, CSRP, CSRP, ctypes.POINTER(ctypes.c_uint32), P, c_size_t, P]),
     "spgemm_chunked_plan": (ctypes.c_int, [CSRP, CSRP, P, c_size_t, c_int32, c_int32, ctypes.POINTER(P)]),
+    "spgemm_chunked_plan_knl": (ctypes.c_int, [CSRP, CSRP, P, c_size_t, c_int32, c_int32, ctypes.POINTER(P)]),
     "spgemm_plan_info_get": (ctypes.c_int, [P, ctypes.POINTER(PlanInfo)]),
     "spgemm_plan_parts": (ctypes.c_int, [P, c_int32, P, c_int32]),
     "spgemm_plan_steps": (ctypes.c_int, [P, ctypes.POINTER(PlanStep), c_int32]),

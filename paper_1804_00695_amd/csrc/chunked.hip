@@ -1,8 +1,10 @@
 // chunked.hip -- executor of the chunking algorithms (Sec. 3.3.1, Algs.
-// "chunk1" and "chunk2"): A, B and C live in pinned host memory (the slow
-// tier); row parts are copied into part buffers carved from the workspace
-// (the fast tier, HBM), multiplied by the row-range fused multiply-add
-// kernel (C_r += A_r[:, P_b] * B_b, Sec. 3.2.2) and copied back.
+// "chunk1" and "chunk2"; Sec. 3.2.2, Alg. "chunkknl"): A, B and C live in
+// pinned host memory (the slow tier); row parts are copied into part buffers
+// carved from the workspace (the fast tier, HBM), multiplied by the
+// row-range fused multiply-add kernel (C_r += A_r[:, P_b] * B_b, Sec. 3.2.2)
+// and copied back. Under chunkknl only B's parts are copied; the kernels use
+// A and C where they are, through the device mapping of the host memory.
 //
 // Copies host->device go on s_h2d, device->host on s_d2h and kernels on
 // s_compute; events order them:
@@ -11,12 +13,16 @@
 //   - a kernel starts after the copies of its A/C part and B part;
 //   - C's partial values are copied back in (Alg. chunk2, second B part on)
 //     only after every earlier copy back has finished.
-// With nbuf_inner = 2 the inner-loop matrix alternates between two buffers,
-// so its next copy overlaps the current kernel (double buffering). Every
-// B part is visited in ascending order and each kernel adds its terms in
-// ascending k, so the result is bit-identical to spgemm_numeric.
+// With nbuf_inner = 2..4 the inner-loop matrix rotates through that many
+// buffers, so its next copies overlap the current kernel. The row binning of
+// each A/C part (which depends only on the row sizes of C) is computed by the
+// part's first kernel step into its own slice of the per-row arrays and kept
+// for the part's later steps. Every B part is visited in ascending order and
+// each kernel adds its terms in ascending k, so the result is bit-identical
+// to spgemm_numeric.
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "../../include/mlspgemm.h"
 #include "common.h"
@@ -102,6 +108,42 @@ void place_b(BBuf &b, const spgemm_csr *B, int32_t r0, int32_t r1)
     b.bval = (double *)p;
 }
 
+// Device addresses of a matrix the kernels use in place (chunkknl's A and C):
+// page-locked host memory through its device mapping, or device memory.
+// *on_host tells whether its row pointers can be read on the host.
+spgemm_status device_csr(spgemm_csr &M, int dev, bool *on_host)
+{
+    bool host = false;
+    const void *q = nullptr;
+    spgemm_status st = device_view(M.row_ptr, dev, &q, &host);
+    if (st != SPGEMM_OK) return st;
+    *on_host = host;
+    M.row_ptr = (int32_t *)q;
+    if (M.nnz > 0) {
+        if ((st = device_view(M.col_idx, dev, &q, &host)) != SPGEMM_OK) return st;
+        M.col_idx = (int32_t *)q;
+        if ((st = device_view(M.values, dev, &q, &host)) != SPGEMM_OK) return st;
+        M.values = (double *)q;
+    }
+    return SPGEMM_OK;
+}
+
+// A matrix the executor copies from or to: every array must be page-locked
+// host memory.
+spgemm_status pinned_csr(const spgemm_csr &M, int dev)
+{
+    const void *arrays[3] = {M.row_ptr, M.nnz > 0 ? M.col_idx : nullptr, M.nnz > 0 ? M.values : nullptr};
+    for (const void *p : arrays) {
+        if (!p) continue;
+        bool host = false;
+        const void *q = nullptr;
+        spgemm_status st = device_view(p, dev, &q, &host);
+        if (st != SPGEMM_OK) return st;
+        if (!host) return SPGEMM_ERR_INVALID_ARG;
+    }
+    return SPGEMM_OK;
+}
+
 // Host row pointers of an operand: start at 0, never decrease, end at nnz.
 bool row_ptr_ok(const int32_t *rp, int32_t n, int64_t nnz)
 {
@@ -115,13 +157,26 @@ bool row_ptr_ok(const int32_t *rp, int32_t n, int64_t nnz)
 
 namespace mls {
 
-spgemm_status numeric_launch(const Batch &b, double avg_b, char *ws, const Layout &L, hipStream_t s)
+// One kernel step of a chunked run over the A/C rows in b. With keep, the
+// rows' binning lives in part `part`'s slice of the per-row arrays and its
+// own bin-count entry of the table; only the part's first step (`first`)
+// computes it. The error word accumulates over the whole run.
+spgemm_status numeric_launch(const Batch &b, double avg_b, char *ws, const Layout &L, int32_t *bin_tbl, bool keep,
+                             int part, int32_t row0, bool first, hipStream_t s)
 {
     Sched sc = make_sched(ws, L);
-    // clear the scheduling counters but keep the error word, so that errors
-    // of every part accumulate until the end of the chunked run
-    launch_fill_i32((int32_t *)(ws + L.hdr + kHdrBinCount), 0, (kHdrBytes - kHdrBinCount) / 4, s);
-    launch_bin(b, kModeNumeric, sc, bin_force(), nullptr, s);
+    if (keep) {
+        sc.val += row0;
+        sc.cls += row0;
+        sc.perm += row0;
+        sc.bin_count = bin_tbl + (size_t)part * kNumBins;
+    }
+    // clear the scheduling counters, keep the error word
+    if (first || !keep)
+        launch_fill_i32((int32_t *)(ws + L.hdr + kHdrBinCount), 0, (kHdrBytes - kHdrBinCount) / 4, s);
+    else
+        launch_fill_i32((int32_t *)(ws + L.hdr + kHdrTaskCursor), 0, kNumBins * kXcd, s);
+    if (first || !keep) launch_bin(b, kModeNumeric, sc, bin_force(), nullptr, s);
     launch_numeric(b, sc, choose_group(avg_b), s);
     return check_launch();
 }
@@ -142,45 +197,103 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
         return SPGEMM_ERR_INVALID_ARG;
     if ((int64_t)ws_bytes < P->ws_bytes) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
     if (((uintptr_t)ws_v & 255) != 0) return SPGEMM_ERR_INVALID_ARG;
+    if (P->nbuf_inner < 1 || P->nbuf_inner > kMaxBuf) return SPGEMM_ERR_INVALID_ARG;
     // the operands must be the ones the plan was cut for: same entry counts
     // and consistent row pointers (the part buffers are sized from them)
     if (A->nnz != P->nnzA || B->nnz != P->nnzB || C->nnz != P->nnzC) return SPGEMM_ERR_DIM_MISMATCH;
-    if (!row_ptr_ok(A->row_ptr, A->nrows, A->nnz) || !row_ptr_ok(B->row_ptr, B->nrows, B->nnz) ||
-        !row_ptr_ok(C->row_ptr, C->nrows, C->nnz))
+    const bool knl = P->algo == kAlgoKnl;
+    // Algs. chunk1 / chunk2: the row pointers of A, B and C are host memory by
+    // contract and must be consistent (the part buffers are sized from them);
+    // checked here before any HIP call
+    if (!knl && (!row_ptr_ok(A->row_ptr, A->nrows, A->nnz) || !row_ptr_ok(B->row_ptr, B->nrows, B->nnz) ||
+                 !row_ptr_ok(C->row_ptr, C->nrows, C->nnz)))
         return SPGEMM_ERR_BAD_CSR;
+    if (!knl) {
+        const int32_t rows_of[4] = {A->nrows, B->nrows, A->nrows, A->nrows};
+        for (const spgemm_plan_step &stp : P->steps)
+            if (stp.row_begin < 0 || stp.row_end < stp.row_begin || stp.matrix < 0 || stp.matrix > 3 ||
+                stp.row_end > rows_of[stp.matrix])
+                return SPGEMM_ERR_INVALID_ARG;
+        const size_t rac0 = al((size_t)P->max_ac) + kRegionSlack;
+        const size_t rb0 = al((size_t)P->max_b) + kRegionSlack;
+        for (const spgemm_plan_step &stp : P->steps) {
+            if (stp.kind != kStepH2D) continue;
+            if (stp.matrix == kMatA && ac_extent(A, C, stp.row_begin, stp.row_end) > rac0) return SPGEMM_ERR_DIM_MISMATCH;
+            if (stp.matrix == kMatB && b_extent(B, stp.row_begin, stp.row_end) > rb0) return SPGEMM_ERR_DIM_MISMATCH;
+        }
+    }
+    int dev = 0;
+    {
+        hipError_t ed = hipGetDevice(&dev);
+        if (ed != hipSuccess) return hip_fail(ed);
+    }
+    // B (and, except under chunkknl, A and C) are copied from and to
+    // page-locked host memory; chunkknl's kernels use A and C in place
+    spgemm_csr Ad = *A, Cd = *C;
+    bool a_host = true, c_host = true;
+    spgemm_status sv = pinned_csr(*B, dev);
+    if (sv == SPGEMM_OK) sv = knl ? device_csr(Ad, dev, &a_host) : pinned_csr(*A, dev);
+    if (sv == SPGEMM_OK) sv = knl ? device_csr(Cd, dev, &c_host) : pinned_csr(*C, dev);
+    if (sv != SPGEMM_OK) return sv;
+    // chunkknl: B's row pointers, and those of A and C when they are in host
+    // memory, must be consistent; A and C in device memory are used as they
+    // are, like spgemm_numeric's operands
+    if (knl && (!row_ptr_ok(B->row_ptr, B->nrows, B->nnz) || (a_host && !row_ptr_ok(A->row_ptr, A->nrows, A->nnz)) ||
+                (c_host && !row_ptr_ok(C->row_ptr, C->nrows, C->nnz))))
+        return SPGEMM_ERR_BAD_CSR;
+    if (knl)
+        for (const spgemm_plan_step &stp : P->steps)
+            if (stp.row_begin < 0 || stp.row_end < stp.row_begin || stp.row_end > B->nrows ||
+                (stp.kind == kStepH2D && b_extent(B, stp.row_begin, stp.row_end) > al((size_t)P->max_b) + kRegionSlack))
+                return SPGEMM_ERR_DIM_MISMATCH;
     char *ws = (char *)ws_v;
     memo_forget(ws_v);
 
     const Layout L = make_layout(1, A->nrows, B->nrows, 0, B->ncols, false);
-    char *buf0 = ws + al(L.total);
+    int32_t *bin_tbl = (int32_t *)(ws + al(L.total));
+    char *buf0 = ws + al(L.total) + binned_parts_bytes();
+    const bool keep = (int64_t)P->p_ac.size() <= kMaxBinnedParts;
+    std::vector<char> binned(P->p_ac.size(), 0);
+    const int nbuf = P->nbuf_inner;
     const size_t rac = al((size_t)P->max_ac) + kRegionSlack;
     const size_t rb = al((size_t)P->max_b) + kRegionSlack;
-    AcBuf acb[2];
-    BBuf bb[2];
+    AcBuf acb[kMaxBuf];
+    BBuf bb[kMaxBuf];
     size_t need;
-    if (P->algo == 1) {
+    if (P->algo == kAlgoChunk1) {
         acb[0].base = buf0;
-        for (int s = 0; s < P->nbuf_inner; ++s) bb[s].base = buf0 + rac + s * rb;
-        need = al(L.total) + rac + P->nbuf_inner * rb;
-    } else {
+        for (int s = 0; s < nbuf; ++s) bb[s].base = buf0 + rac + s * rb;
+        need = (size_t)(buf0 - ws) + rac + nbuf * rb;
+    } else if (P->algo == kAlgoChunk2) {
         bb[0].base = buf0;
-        for (int s = 0; s < P->nbuf_inner; ++s) acb[s].base = buf0 + rb + s * rac;
-        need = al(L.total) + rb + P->nbuf_inner * rac;
+        for (int s = 0; s < nbuf; ++s) acb[s].base = buf0 + rb + s * rac;
+        need = (size_t)(buf0 - ws) + rb + nbuf * rac;
+    } else {
+        for (int s = 0; s < nbuf; ++s) bb[s].base = buf0 + s * rb;
+        need = (size_t)(buf0 - ws) + nbuf * rb;
     }
     if (need > ws_bytes) return SPGEMM_ERR_WORKSPACE_TOO_SMALL;
-    // every part of the schedule must fit its buffer region before anything
-    // is queued
+    // every part of the schedule must fit its buffer region, and every step
+    // must name a part and a buffer of the plan, before anything is queued
     for (const spgemm_plan_step &stp : P->steps) {
+        if (stp.slot < 0 || stp.slot >= nbuf) return SPGEMM_ERR_INVALID_ARG;
+        if (stp.kind == kStepKernel && (stp.part < 0 || stp.part >= (int)P->p_ac.size())) return SPGEMM_ERR_INVALID_ARG;
         if (stp.kind != kStepH2D) continue;
         if (stp.row_begin < 0 || stp.row_end < stp.row_begin) return SPGEMM_ERR_INVALID_ARG;
-        if (stp.matrix == kMatA && ac_extent(A, C, stp.row_begin, stp.row_end) > rac)
+        if (stp.matrix == kMatA && (knl || ac_extent(A, C, stp.row_begin, stp.row_end) > rac))
             return SPGEMM_ERR_DIM_MISMATCH;
         if (stp.matrix == kMatB && b_extent(B, stp.row_begin, stp.row_end) > rb) return SPGEMM_ERR_DIM_MISMATCH;
     }
 
-    Ev ev_b_ready[2], ev_ac_ready[2], ev_kdone[2], ev_d2h[2], ev_outer_free, ev_last_kernel, ev_last_d2h;
-    Ev *all[] = {&ev_b_ready[0], &ev_b_ready[1], &ev_ac_ready[0], &ev_ac_ready[1], &ev_kdone[0], &ev_kdone[1],
-                 &ev_d2h[0], &ev_d2h[1], &ev_outer_free, &ev_last_kernel, &ev_last_d2h};
+    Ev ev_b_ready[kMaxBuf], ev_ac_ready[kMaxBuf], ev_kdone[kMaxBuf], ev_d2h[kMaxBuf];
+    Ev ev_outer_free, ev_last_kernel, ev_last_d2h;
+    std::vector<Ev *> all = {&ev_outer_free, &ev_last_kernel, &ev_last_d2h};
+    for (int s = 0; s < kMaxBuf; ++s) {
+        all.push_back(&ev_b_ready[s]);
+        all.push_back(&ev_ac_ready[s]);
+        all.push_back(&ev_kdone[s]);
+        all.push_back(&ev_d2h[s]);
+    }
     hipError_t e = hipSuccess;
     for (Ev *x : all)
         if (e == hipSuccess) e = hipEventCreateWithFlags(&x->e, hipEventDisableTiming);
@@ -216,7 +329,8 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
         e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s_d);
         issued_d += (int64_t)bytes;
     };
-    const bool ac_outer = P->algo == 1;
+    const bool ac_outer = P->algo != kAlgoChunk2;   // chunk1 and chunkknl keep A/C in place over the B loop
+    int kernels_done = 0;
 
     for (const spgemm_plan_step &stp : P->steps) {
         if (e != hipSuccess || st != SPGEMM_OK) break;
@@ -265,30 +379,48 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
             break;
         }
         case kStepKernel: {
-            AcBuf &a = acb[sac];
             BBuf &bq = bb[sb];
-            e = ev_ac_ready[sac].wait(s_c);
-            if (e == hipSuccess) e = ev_b_ready[sb].wait(s_c);
-            if (e != hipSuccess) break;
+            e = ev_b_ready[sb].wait(s_c);
             Batch bt;
             std::memset(&bt, 0, sizeof(bt));
             bt.nprob = 1;
-            bt.na = a.r1 - a.r0;
             bt.max_ncols = g_opt.wide_table ? 0 : B->ncols;
             Prob &q = bt.p0;
-            q.arp = a.arp; q.aci = a.aci; q.aval = a.aval;
+            int32_t a_r0, a_r1;
+            if (knl) {
+                // A and C in place, all rows; the first B part writes C's
+                // values, the later ones add onto them
+                a_r0 = 0;
+                a_r1 = A->nrows;
+                q.arp = Ad.row_ptr; q.aci = Ad.col_idx; q.aval = Ad.values;
+                q.crp = Cd.row_ptr; q.cci = Cd.col_idx; q.cval = Cd.values;
+                q.a_off = 0;
+                q.c_off = 0;
+                q.accumulate = kernels_done > 0 ? 1 : 0;
+            } else {
+                AcBuf &a = acb[sac];
+                if (e == hipSuccess) e = ev_ac_ready[sac].wait(s_c);
+                a_r0 = a.r0;
+                a_r1 = a.r1;
+                q.arp = a.arp; q.aci = a.aci; q.aval = a.aval;
+                q.crp = a.crp; q.cci = a.cci; q.cval = a.cval;
+                q.a_off = A->row_ptr[a.r0];
+                q.c_off = C->row_ptr[a.r0];
+                q.accumulate = 1;
+            }
+            if (e != hipSuccess) break;
+            bt.na = a_r1 - a_r0;
             q.brp = bq.brp; q.bci = bq.bci; q.bval = bq.bval;
-            q.crp = a.crp; q.cci = a.cci; q.cval = a.cval;
-            q.nrows = a.r1 - a.r0;
+            q.nrows = a_r1 - a_r0;
             q.ncols = B->ncols;
             q.krows = bq.r1 - bq.r0;
-            q.a_off = A->row_ptr[a.r0];
             q.b_off = B->row_ptr[bq.r0];
-            q.c_off = C->row_ptr[a.r0];
             q.k_lo = bq.r0;
             q.k_hi = bq.r1;
-            q.accumulate = 1;
-            st = numeric_launch(bt, avg_b, ws, L, s_c);
+            const bool first = !binned[stp.part];
+            st = numeric_launch(bt, avg_b, ws, L, bin_tbl, keep, stp.part, a_r0, first, s_c);
+            binned[stp.part] = 1;
+            ++kernels_done;
             if (st == SPGEMM_OK) e = ev_kdone[ac_outer ? sb : sac].record(s_c);
             if (e == hipSuccess) e = ev_last_kernel.record(s_c);
             break;

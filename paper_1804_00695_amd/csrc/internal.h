@@ -72,6 +72,10 @@ spgemm_status prepare_batch(int32_t nbatch, const spgemm_csr *A, const spgemm_cs
 spgemm_status run_symbolic(BatchHost &bh, char *ws, int fill, int64_t *nnz_host, hipStream_t s);
 spgemm_status run_numeric(BatchHost &bh, char *ws, hipStream_t s);
 int choose_group(double avg);
+// Address the device uses for p: device memory of device `dev` unchanged,
+// page-locked host memory through its device mapping (*on_host set);
+// pageable, managed or another device's memory is SPGEMM_ERR_INVALID_ARG.
+spgemm_status device_view(const void *p, int dev, const void **out, bool *on_host);
 void memo_forget(const void *ws);
 int pow2_group(double avg);
 

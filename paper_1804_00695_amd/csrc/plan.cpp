@@ -1,6 +1,8 @@
 // plan.cpp -- chunking decision of Sec. 3.3.1 (Alg. "chunker", the Partition
 // heuristic) and the copy schedules of Algs. "chunk1" (A/C parts in place, B
-// streams) and "chunk2" (B parts in place, A/C stream). Host only.
+// streams) and "chunk2" (B parts in place, A/C stream); and the partition of
+// Sec. 3.2.2 (Alg. "chunkknl": only B is cut into parts that stream into fast
+// memory, A and C stay in the slow tier and are accessed in place). Host only.
 //
 // Sizes: a row range [r0, r1) of a CSR matrix occupies 4*(r1 - r0 + 1) bytes
 // of row pointers plus 12 bytes per entry (int32 index, fp64 value); C counts
@@ -13,14 +15,16 @@
 // the big portion goes to the inner-loop matrix. Copy costs count the bytes
 // each schedule really moves, in both directions; ties go to the algorithm the
 // branch favours. nbuf > 1 divides the inner matrix's portion among that many
-// buffers (double buffering); min_parts > 1 cuts the inner matrix into at
-// least that many parts so that transfers of consecutive parts overlap.
+// buffers (double, triple, quadruple buffering); min_parts > 1 cuts the inner
+// matrix into at least that many parts so that transfers of consecutive parts
+// overlap even when it fits whole.
 #include <algorithm>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "../../include/mlspgemm.h"
+#include "common.h"
 #include "internal.h"
 #include "plan.h"
 
@@ -192,17 +196,66 @@ spgemm_status partition(PlanImpl &P, const int32_t *arp, int32_t nA, const int32
     return SPGEMM_OK;
 }
 
+spgemm_status partition_knl(PlanImpl &P, const int32_t *arp, int32_t nA, const int32_t *brp, int32_t nB,
+                            const int32_t *crp, int64_t fast, int nbuf, int min_parts)
+{
+    // np = ceil(size(B) / FastSize), pSize = size(B) / np, P_B = BinarySearch(B, pSize);
+    // with nbuf buffers each part gets FastSize / nbuf
+    P.fast = fast;
+    P.branch = 0;
+    P.algo = kAlgoKnl;
+    P.nbuf_inner = nbuf;
+    const int64_t sB = rows_bytes(brp, 0, nB);
+    int64_t max_row_b = 0;
+    for (int32_t k = 0; k < nB; ++k) max_row_b = std::max<int64_t>(max_row_b, 8 + 12ll * ((int64_t)brp[k + 1] - brp[k]));
+    auto size_b = [&](int32_t r0, int32_t r1) { return rows_bytes(brp, r0, r1); };
+    int64_t ps = 0;
+    if (!balanced(sB, fast / nbuf, max_row_b, min_parts, ps) || !cut_parts(size_b, nB, ps, P.p_b)) return SPGEMM_ERR_BUDGET;
+    P.p_ac.assign(1, Part{0, nA});
+    int64_t b = 0;
+    for (auto &p : P.p_b) b += rows_bytes(brp, p.r0, p.r1);
+    P.h2d = b;
+    P.d2h = 0;
+    P.cost1 = P.cost2 = 0;
+    const int64_t nparts = (int64_t)P.p_b.size();
+    const int64_t cval = 8ll * ((int64_t)crp[nA] - crp[0]);
+    // every pass reads A and C's structure in place and writes C's values;
+    // passes after the first also read the values the previous one wrote
+    P.zero_copy = nparts * (rows_bytes(arp, 0, nA) + struct_bytes(crp, 0, nA)) + nparts * cval + (nparts - 1) * cval;
+    P.max_ac = 0;
+    P.max_b = 0;
+    for (auto &p : P.p_b) P.max_b = std::max<int64_t>(P.max_b, size_b(p.r0, p.r1));
+    P.chunk_bytes = nbuf * P.max_b;
+    P.max_ac_rows = nA;
+    P.steps.clear();
+    for (int q = 0; q < (int)P.p_b.size(); ++q) {
+        spgemm_plan_step s;
+        s.kind = kStepH2D; s.matrix = kMatB; s.part = q; s.row_begin = P.p_b[q].r0; s.row_end = P.p_b[q].r1;
+        s.slot = q % nbuf; s.bytes = rows_bytes(brp, s.row_begin, s.row_end);
+        P.steps.push_back(s);
+        s.kind = kStepKernel; s.matrix = kMatCVal; s.part = 0; s.bytes = 0;
+        P.steps.push_back(s);
+    }
+    return SPGEMM_OK;
+}
+
+int64_t binned_parts_bytes()
+{
+    return ((int64_t)kMaxBinnedParts * kNumBins * 4 + 255) & ~(int64_t)255;
+}
+
 }  // namespace mls
 
 using namespace mls;
 
 extern "C" {
 
-spgemm_status spgemm_chunked_plan(const spgemm_csr *A, const spgemm_csr *B, const int32_t *C_row_ptr,
-                                  size_t hbm_budget_bytes, int32_t nbuf, int32_t min_parts, spgemm_plan **plan_out)
+static spgemm_status make_plan(const spgemm_csr *A, const spgemm_csr *B, const int32_t *C_row_ptr,
+                               size_t hbm_budget_bytes, int32_t nbuf, int32_t min_parts, bool knl,
+                               spgemm_plan **plan_out)
 {
     if (!A || !B || !C_row_ptr || !plan_out || !A->row_ptr || !B->row_ptr) return SPGEMM_ERR_INVALID_ARG;
-    if (nbuf < 1 || nbuf > 2 || min_parts < 1) return SPGEMM_ERR_INVALID_ARG;
+    if (nbuf < 1 || nbuf > kMaxBuf || min_parts < 1) return SPGEMM_ERR_INVALID_ARG;
     if (A->ncols != B->nrows) return SPGEMM_ERR_DIM_MISMATCH;
     *plan_out = nullptr;
     PlanImpl *P = new (std::nothrow) PlanImpl();
@@ -214,15 +267,32 @@ spgemm_status spgemm_chunked_plan(const spgemm_csr *A, const spgemm_csr *B, cons
     P->nnzB = B->row_ptr[B->nrows];
     P->nnzC = C_row_ptr[A->nrows];
     // reserve: the numeric kernels' per-row arrays for up to all rows of A,
-    // plus alignment slack of the part buffers
-    P->reserve = (int64_t)make_layout(1, A->nrows, B->nrows, 0, B->ncols, false).total + kChunkSlack;
+    // the kept binnings of the A/C parts, and alignment slack of the part buffers
+    P->reserve = (int64_t)make_layout(1, A->nrows, B->nrows, 0, B->ncols, false).total + binned_parts_bytes() +
+                 kChunkSlack;
     int64_t fast = (int64_t)hbm_budget_bytes - P->reserve;
     if (fast <= 0) { delete P; return SPGEMM_ERR_BUDGET; }
-    spgemm_status st = partition(*P, A->row_ptr, A->nrows, B->row_ptr, B->nrows, C_row_ptr, fast, nbuf, min_parts);
+    spgemm_status st = knl ? partition_knl(*P, A->row_ptr, A->nrows, B->row_ptr, B->nrows, C_row_ptr, fast, nbuf,
+                                           min_parts)
+                           : partition(*P, A->row_ptr, A->nrows, B->row_ptr, B->nrows, C_row_ptr, fast, nbuf,
+                                       min_parts);
     if (st != SPGEMM_OK) { delete P; return st; }
     P->ws_bytes = P->reserve + P->chunk_bytes;
     *plan_out = reinterpret_cast<spgemm_plan *>(P);
     return SPGEMM_OK;
+}
+
+spgemm_status spgemm_chunked_plan(const spgemm_csr *A, const spgemm_csr *B, const int32_t *C_row_ptr,
+                                  size_t hbm_budget_bytes, int32_t nbuf, int32_t min_parts, spgemm_plan **plan_out)
+{
+    return make_plan(A, B, C_row_ptr, hbm_budget_bytes, nbuf, min_parts, false, plan_out);
+}
+
+spgemm_status spgemm_chunked_plan_knl(const spgemm_csr *A, const spgemm_csr *B, const int32_t *C_row_ptr,
+                                      size_t hbm_budget_bytes, int32_t nbuf, int32_t min_parts,
+                                      spgemm_plan **plan_out)
+{
+    return make_plan(A, B, C_row_ptr, hbm_budget_bytes, nbuf, min_parts, true, plan_out);
 }
 
 spgemm_status spgemm_plan_info_get(const spgemm_plan *plan, spgemm_plan_info *out)
@@ -245,6 +315,7 @@ spgemm_status spgemm_plan_info_get(const spgemm_plan *plan, spgemm_plan_info *ou
     out->ws_bytes = P->ws_bytes;
     out->issued_h2d = P->issued_h2d;
     out->issued_d2h = P->issued_d2h;
+    out->zero_copy_bytes = P->zero_copy;
     return SPGEMM_OK;
 }
 

@@ -1,9 +1,12 @@
 """GPU parity of the chunked numeric phase (pinned host A, B, C; HBM budget).
 
-For budgets from "everything fits" down to dozens of parts, with single and
-double buffering: C's values must equal the oracle's bit for bit (and the
-in-HBM GPU result), and the bytes the executor queued must equal the plan's
-schedule (which equals the oracle planner's, see test_plan_parity)."""
+For budgets from "everything fits" down to dozens of parts, with single,
+double, triple and quadruple buffering: C's values must equal the oracle's
+bit for bit (and the in-HBM GPU result), and the bytes the executor queued
+must equal the plan's schedule (which equals the oracle planner's, see
+test_plan_parity). Alg. "chunkknl" (only B's parts are copied; the kernels
+use A and C in place, in pinned host memory or in HBM) is held to the same
+bar."""
 import numpy as np
 import pytest
 import torch
@@ -33,10 +36,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 1), (2, 4)])
-def test_chunked_bitwise(case, nbuf, min_parts):
-    kind, n, frac = case
+def case_inputs(kind, n):
     if kind == "stencil":
         A = synth.stencil27_3d(n, amp=0.1)
         B = A
@@ -47,6 +47,15 @@ def test_chunked_bitwise(case, nbuf, min_parts):
     else:
         A = synth.poisson_csr(3000, 2500, 6.0, 41)
         B = synth.poisson_csr(2500, 2800, 9.0, 42)
+    return A, B
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 1), (2, 4), (3, 1), (4, 5)])
+def test_chunked_bitwise(case, nbuf, min_parts):
+    kind, n, frac = case
+    print(f"chunked {case} nbuf={nbuf} min_parts={min_parts}", flush=True)
+    A, B = case_inputs(kind, n)
     R, cabs = oracle.spgemm(A, B)
     total = op.range_bytes(A.row_ptr, 0, A.nrows) + op.range_bytes(B.row_ptr, 0, B.nrows) + \
         op.range_bytes(R.row_ptr, 0, R.nrows)
@@ -98,3 +107,54 @@ def test_chunked_after_unsynchronised_product_on_same_workspace():
         torch.cuda.synchronize()
         assert np.array_equal(Ch.values.numpy(), R.values)
         assert np.array_equal(C.values.cpu().numpy(), R.values)
+
+
+@pytest.mark.parametrize("case", [("stencil", 12, 2.0), ("stencil", 12, 0.3), ("stencil", 12, 0.06),
+                                  ("poisson", 0, 0.25), ("rmat", 12, 0.2)])
+@pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 3), (4, 1)])
+@pytest.mark.parametrize("ac_where", ["pinned", "hbm"])
+def test_knl_bitwise(case, nbuf, min_parts, ac_where):
+    kind, n, frac = case
+    print(f"chunkknl {case} nbuf={nbuf} min_parts={min_parts} A,C in {ac_where}", flush=True)
+    A, B = case_inputs(kind, n)
+    R, _ = oracle.spgemm(A, B)
+    sB = op.range_bytes(B.row_ptr, 0, B.nrows)
+    base = mls.chunked_plan(A.row_ptr, B.row_ptr, B.ncols, R.row_ptr, 10**10, knl=True).info
+    budget = base["ws_bytes"] - base["chunk_bytes"] + int(sB * frac)
+    try:
+        plan = mls.chunked_plan(A.row_ptr, B.row_ptr, B.ncols, R.row_ptr, budget, nbuf=nbuf, min_parts=min_parts,
+                                knl=True)
+    except mls.SpgemmError as e:
+        assert "BUDGET" in str(e)
+        pytest.skip("budget below a single row")
+    Cs = synth.Csr(R.nrows, R.ncols, R.row_ptr, R.col_idx, np.full(R.nnz, np.nan))
+    place = mls.HostCsr.from_host if ac_where == "pinned" else mls.DeviceCsr.from_host
+    Ax, Cx = place(A), place(Cs)
+    mls.numeric_chunked(Ax, mls.HostCsr.from_host(B), Cx, plan)
+    torch.cuda.synchronize()
+    vals = Cx.values.numpy() if ac_where == "pinned" else Cx.values.cpu().numpy()
+    assert np.array_equal(vals, R.values)
+    info = plan.info
+    assert info["algo"] == 3 and info["issued_h2d"] == info["h2d_bytes"] and info["issued_d2h"] == 0
+    assert info["ws_bytes"] <= budget
+    if frac < 1.0:
+        assert info["n_b_parts"] > 1
+
+
+def test_knl_refuses_pageable_a():
+    A, B = case_inputs("poisson", 0)
+    R, _ = oracle.spgemm(A, B)
+    plan = mls.chunked_plan(A.row_ptr, B.row_ptr, B.ncols, R.row_ptr, 10**9, knl=True)
+    Cd = mls.DeviceCsr.from_host(synth.Csr(R.nrows, R.ncols, R.row_ptr, R.col_idx, np.zeros(R.nnz)))
+    Ad = mls.DeviceCsr.from_host(A)
+    Bh = mls.HostCsr.from_host(B)
+    import ctypes
+    keep = np.ascontiguousarray(A.values)          # pageable host memory
+    ha = mls.CsrT(A.nrows, A.ncols, A.nnz, Ad.row_ptr.data_ptr(), Ad.col_idx.data_ptr(), keep.ctypes.data)
+    ws = mls.Workspace()
+    nb = plan.info["ws_bytes"]
+    st = mls.ChunkStreams()
+    rc = mls.lib.spgemm_numeric_chunked(ctypes.byref(ha), ctypes.byref(Bh.handle()), ctypes.byref(Cd.handle()),
+                                        plan._h, ws.get(nb), nb, st.compute.cuda_stream, st.h2d.cuda_stream,
+                                        st.d2h.cuda_stream)
+    assert rc == 1

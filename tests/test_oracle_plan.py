@@ -10,7 +10,10 @@
   part of B; a problem that fits is copied in once and its result out once;
 * executing a schedule on the CPU (row-range products C += A_r[:, b] B_b with
   the parts taken from the fast-memory buffers) gives A*B, and no buffer is
-  overwritten while a pending step still needs its contents.
+  overwritten while a pending step still needs its contents;
+* Alg. "chunkknl": ceil(size(B) / FastSize) parts of at most the balanced
+  size, B not cut when it fits (the data-placement case), B copied once, and
+  its schedule executed on the CPU with A and C left in slow memory gives A*B.
 """
 import numpy as np
 import pytest
@@ -175,8 +178,12 @@ def simulate(plan, A, B, C_struct):
     """
     Ad, Bd = synth.to_dense(A), synth.to_dense(B)
     slow_C = np.zeros((A.nrows, B.ncols))
-    outer_is_ac = plan.algo == op.CHUNK1
+    outer_is_ac = plan.algo in (op.CHUNK1, op.CHUNKKNL)
     buf_a, buf_c, buf_b = {}, {}, {}
+    if plan.algo == op.CHUNKKNL:
+        # A and C stay in slow memory and are used in place
+        buf_a[0] = (0, A.nrows, Ad)
+        buf_c[0] = [0, A.nrows, slow_C]
     for kind, mat, part, r0, r1, nbytes, slot in plan.steps:
         s_ac = 0 if outer_is_ac else slot
         s_b = slot if outer_is_ac else 0
@@ -222,3 +229,48 @@ def test_schedule_executes_to_product(budget_div, nbuf, min_parts):
     assert p.h2d == count_bytes(p.steps, op.H2D, op.MAT_A) + count_bytes(p.steps, op.H2D, op.MAT_B) + \
         count_bytes(p.steps, op.H2D, op.MAT_CSTRUCT) + count_bytes(p.steps, op.H2D, op.MAT_CVAL)
     assert p.d2h == count_bytes(p.steps, op.D2H, op.MAT_CVAL)
+
+
+@pytest.mark.parametrize("lenB,nbuf", [(5, 1), (17, 1), (9, 2), (9, 3), (9, 4)])
+def test_knl_parts_follow_the_algorithm(lenB, nbuf):
+    arp, brp, crp = mats(400, 3000, 7, lenB, 20)
+    sA, sB, sC = sizes(arp, brp, crp)
+    for div in (1.0, 2.5, 7.0, 19.0):
+        fast = int(sB / div) + 64
+        p = op.partition_knl(arp, brp, crp, fast, nbuf=nbuf)
+        np_ = -(-sB // (fast // nbuf))        # ceil(size(B) / portion)
+        psize = -(-sB // np_)
+        assert p.algo == op.CHUNKKNL and p.p_ac == [(0, 400)]
+        assert p.p_b[0][0] == 0 and p.p_b[-1][1] == 3000
+        assert all(b == c for (_, b), (c, _) in zip(p.p_b, p.p_b[1:]))
+        assert all(op.range_bytes(brp, a, b) <= psize for a, b in p.p_b)
+        # uniform rows: the balanced size is met by np or np + 1 greedy parts
+        assert len(p.p_b) in (np_, np_ + 1)
+        assert p.h2d == sum(op.range_bytes(brp, a, b) for a, b in p.p_b) and p.d2h == 0
+        assert p.ws_chunks <= fast
+        assert [s[6] for s in p.steps if s[0] == op.KERNEL] == [i % nbuf for i in range(len(p.p_b))]
+
+
+def test_knl_b_fits_is_not_cut():
+    arp, brp, crp = mats(400, 300, 7, 9, 20)
+    sA, sB, sC = sizes(arp, brp, crp)
+    p = op.partition_knl(arp, brp, crp, 4 * sB)
+    assert p.p_b == [(0, 300)] and p.h2d == sB
+    cval = 8 * int(crp[-1])
+    assert p.zero_copy == sA + (sC - cval) + cval     # one pass: A, C's structure read, C's values written
+
+
+@pytest.mark.parametrize("budget_div", [1, 3, 6, 12])
+@pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 1), (3, 4)])
+def test_knl_schedule_executes_to_product(budget_div, nbuf, min_parts):
+    A = synth.poisson_csr(120, 90, 6.0, 62)
+    B = synth.poisson_csr(90, 110, 7.0, 63)
+    C, _ = oracle.spgemm(A, B)
+    sB = op.range_bytes(B.row_ptr, 0, B.nrows)
+    try:
+        p = op.partition_knl(A.row_ptr, B.row_ptr, C.row_ptr, sB * 2 // budget_div, nbuf=nbuf, min_parts=min_parts)
+    except op.BudgetError:
+        pytest.skip("budget below one row")
+    got = simulate(p, A, B, C)
+    ref = synth.to_dense(A) @ synth.to_dense(B)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)

@@ -31,7 +31,7 @@ def size(rp):
 
 @pytest.mark.parametrize("case", range(13))
 @pytest.mark.parametrize("frac", [10.0, 1.0, 0.5, 0.2, 0.07])
-@pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 1), (2, 5)])
+@pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 1), (2, 5), (3, 1), (4, 6)])
 def test_planner_matches_oracle(case, frac, nbuf, min_parts):
     arp, brp, crp = shapes()[case]
     total = size(arp) + size(brp) + size(crp)
@@ -73,3 +73,37 @@ def test_real_product_plan():
         p = mls.chunked_plan(A.row_ptr, A.row_ptr, A.ncols, C.row_ptr, int(total * frac) + 2_000_000, nbuf=2)
         ref = op.partition(A.row_ptr, A.row_ptr, C.row_ptr, p.info["fast_bytes"], nbuf=2)
         assert p.steps() == [tuple(s) for s in ref.steps]
+
+
+@pytest.mark.parametrize("case", range(13))
+@pytest.mark.parametrize("frac", [4.0, 1.0, 0.3, 0.08])
+@pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 1), (3, 4), (4, 1)])
+def test_knl_planner_matches_oracle(case, frac, nbuf, min_parts):
+    arp, brp, crp = shapes()[case]
+    budget = int(size(brp) * frac) + 100000
+    try:
+        p = mls.chunked_plan(arp, brp, 10**6, crp, budget, nbuf=nbuf, min_parts=min_parts, knl=True)
+    except mls.SpgemmError as e:
+        assert "BUDGET" in str(e)
+        big = mls.chunked_plan(arp, brp, 10**6, crp, 100 * size(brp) + 10**8, nbuf=nbuf, knl=True)
+        fast = budget - (100 * size(brp) + 10**8 - big.info["fast_bytes"])
+        if fast > 0:
+            with pytest.raises(op.BudgetError):
+                op.partition_knl(arp, brp, crp, fast, nbuf=nbuf, min_parts=min_parts)
+        return
+    info = p.info
+    ref = op.partition_knl(arp, brp, crp, info["fast_bytes"], nbuf=nbuf, min_parts=min_parts)
+    assert info["algo"] == 3 and info["branch"] == 0
+    assert p.parts(0) == [tuple(x) for x in ref.p_ac]
+    assert p.parts(1) == [tuple(x) for x in ref.p_b]
+    assert (info["h2d_bytes"], info["d2h_bytes"], info["zero_copy_bytes"]) == (ref.h2d, ref.d2h, ref.zero_copy)
+    assert info["chunk_bytes"] == ref.ws_chunks and info["nbuf_inner"] == nbuf
+    assert p.steps() == [tuple(s) for s in ref.steps]
+    assert info["ws_bytes"] <= budget
+
+
+def test_nbuf_range():
+    arp, brp, crp = shapes()[0]
+    for bad in (0, 5):
+        with pytest.raises(mls.SpgemmError, match="INVALID_ARG"):
+            mls.chunked_plan(arp, brp, 10**6, crp, 10**9, nbuf=bad)
