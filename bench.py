@@ -466,8 +466,10 @@ def bench_batched(torch, mls, synth, with_parity):
         mls.batch_numeric(Rs, APs, Acs, ws)
         return APs, Acs
 
+    log("batched: inputs ready; per-call path")
     per_call()
     t_call, _ = timed(torch, per_call, 3)
+    log("batched: per-call timed")
     APs, Acs = batched()
     t_batch, _ = timed(torch, batched, 3)
     # the stages one at a time
@@ -482,6 +484,7 @@ def bench_batched(torch, mls, synth, with_parity):
         plan1.run()
         plan2.run()
 
+    log("batched: stages timed; graph replay next")
     replay()
     t_replay, _ = timed(torch, replay, 5)
     t_rep1, _ = timed(torch, plan1.run, 5)
@@ -566,6 +569,7 @@ def bench_backward(torch, mls, synth, with_parity):
     Wv = synth.normal_values(C.nnz, 7)
     W = mls.DeviceCsr(C.nrows, C.ncols, C.row_ptr, C.col_idx, torch.from_numpy(Wv).cuda())
     _, madds = mls.row_work(dA, dB, ws)
+    log("backward: inputs ready")
     fwd = lambda: mls.numeric(dA, dB, C, ws)
     bwd = lambda: mls.backward(dA, dB, W, ws=ws, check_structure=False)
     det = lambda: mls.backward(dA, dB, W, ws=ws, deterministic=True, check_structure=False)
@@ -578,6 +582,7 @@ def bench_backward(torch, mls, synth, with_parity):
     t_d, _ = timed(torch, det, 5, pre=flush)
     t_f_warm, _ = timed(torch, fwd, 5)
     t_b_warm, _ = timed(torch, bwd, 5)
+    log("backward: fused timed; unfused per-call path next")
     unf()
     t_u, _ = timed(torch, unf, 2, pre=flush)
     prof_f = profiled(torch, mls, lambda: (flush(), fwd()), 5)

@@ -156,6 +156,27 @@ spgemm_status spgemm_symbolic(const spgemm_csr *A, const spgemm_csr *B, int32_t 
                               int32_t *C_col_idx, int64_t *nnzC_host, void *ws, size_t ws_bytes,
                               hipStream_t stream);
 
+/* Symbolic phase under an HBM budget, for products whose structure does not
+ * fit the fast memory (the paper chunks only the numeric phase; this carries
+ * its row-part idea over to Sec. 2.1's symbolic phase). A_host and B_host
+ * hold host arrays (row_ptr, col_idx; values unused); C_row_ptr_host and
+ * C_col_idx_host are host arrays too. The workspace (device memory) is the
+ * budget: B's compressed pattern (8 bytes per entry of B plus 8 per row)
+ * stays in it while row parts of A stream through, so every byte the call
+ * uses lies in [ws, ws + ws_bytes). Same two passes as spgemm_symbolic:
+ *   count (C_col_idx_host == NULL): writes C_row_ptr_host[A.nrows + 1] and
+ *     *nnzC_host (may be NULL);
+ *   fill (C_col_idx_host != NULL): C_row_ptr_host must hold the count
+ *     pass's result; writes the ascending, unique columns of every row.
+ * A and B are validated on the device part by part when SPGEMM_OPT_VALIDATE
+ * is on. Synchronises the stream (one synchronisation per part). The result
+ * equals spgemm_symbolic's. Errors: SPGEMM_ERR_BUDGET when B's compressed
+ * pattern and one row of A (and of C) do not fit ws_bytes, SPGEMM_ERR_BAD_CSR,
+ * SPGEMM_ERR_DIM_MISMATCH, SPGEMM_ERR_INDEX_OVERFLOW (nnz(C) >= 2^31). */
+spgemm_status spgemm_symbolic_chunked(const spgemm_csr *A_host, const spgemm_csr *B_host,
+                                      int32_t *C_row_ptr_host, int32_t *C_col_idx_host, int64_t *nnzC_host,
+                                      void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Numeric phase (Sec. 2.1, Fig. "spgemmexp"): C->values[e] = sum over k of
  * a_ik * b_kj for every stored (i, j) of C, terms added in ascending k.
  * C->row_ptr and C->col_idx must be the symbolic phase's result (any

@@ -217,6 +217,31 @@ def symbolic(A: DeviceCsr, B: DeviceCsr, ws: Optional[Workspace] = None, with_va
     return DeviceCsr(A.nrows, B.ncols, crp, cci[:nnz.value], None if vals is None else vals[:nnz.value])
 
 
+def symbolic_chunked(A, B, budget: int, ws: Optional[Workspace] = None, device="cuda"):
+    """Structure of C = A*B under an HBM budget (bytes of device workspace):
+    A and B are host CSR (numpy arrays: row_ptr, col_idx); returns host
+    (row_ptr, col_idx) of C. B's compressed pattern stays in HBM while row
+    parts of A stream through."""
+    def host(M):
+        rp = np.ascontiguousarray(M.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(M.col_idx, dtype=np.int32)
+        return CsrT(int(M.nrows), int(M.ncols), int(rp[-1]), rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                    None), (rp, ci)
+    ha, keep_a = host(A)
+    hb, keep_b = host(B)
+    w = _ws(ws, device)
+    p = w.get(int(budget))
+    s = stream_handle()
+    crp = np.zeros(int(A.nrows) + 1, dtype=np.int32)
+    nnz = ctypes.c_int64(0)
+    check(lib.spgemm_symbolic_chunked(ctypes.byref(ha), ctypes.byref(hb), crp.ctypes.data, None, ctypes.byref(nnz),
+                                      p, int(budget), s), "spgemm_symbolic_chunked(count)")
+    cci = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    check(lib.spgemm_symbolic_chunked(ctypes.byref(ha), ctypes.byref(hb), crp.ctypes.data, cci.ctypes.data, None,
+                                      p, int(budget), s), "spgemm_symbolic_chunked(fill)")
+    return crp, cci[:nnz.value]
+
+
 def numeric(A: DeviceCsr, B: DeviceCsr, C: DeviceCsr, ws: Optional[Workspace] = None) -> DeviceCsr:
     """Numeric phase: fills C.values on C's structure."""
     dev = A.row_ptr.device

@@ -52,6 +52,7 @@ SIGNATURES = {
     "spgemm_compress": (ctypes.c_int, [CSRP, P, P, P, c_size_t, P]),
     "spgemm_symbolic": (ctypes.c_int, [CSRP, CSRP, P, P, I64P, P, c_size_t, P]),
     "spgemm_numeric": (ctypes.c_int, [CSRP, CSRP, CSRP, P, c_size_t, P]),
+    "spgemm_symbolic_chunked": (ctypes.c_int, [CSRP, CSRP, P, P, I64P, P, c_size_t, P]),
     "spgemm_check_errors": (ctypes.c_int, [P, c_size_t, P]),
     "spgemm_numeric_noalloc": (ctypes.c_int, [CSRP, CSRP, CSRP, P]),
     "spgemm_numeric_placed": (ctypes.c_int, [CSRP, CSRP, CSRP, ctypes.POINTER(ctypes.c_uint32), P, c_size_t, P]),

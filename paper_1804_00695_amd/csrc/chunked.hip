@@ -209,11 +209,13 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
                  !row_ptr_ok(C->row_ptr, C->nrows, C->nnz)))
         return SPGEMM_ERR_BAD_CSR;
     if (!knl) {
-        const int32_t rows_of[4] = {A->nrows, B->nrows, A->nrows, A->nrows};
-        for (const spgemm_plan_step &stp : P->steps)
+        // kernel steps carry B's row range, the others the rows of their matrix
+        for (const spgemm_plan_step &stp : P->steps) {
+            const int32_t rows = (stp.kind == kStepKernel || stp.matrix == kMatB) ? B->nrows : A->nrows;
             if (stp.row_begin < 0 || stp.row_end < stp.row_begin || stp.matrix < 0 || stp.matrix > 3 ||
-                stp.row_end > rows_of[stp.matrix])
+                stp.row_end > rows)
                 return SPGEMM_ERR_INVALID_ARG;
+        }
         const size_t rac0 = al((size_t)P->max_ac) + kRegionSlack;
         const size_t rb0 = al((size_t)P->max_b) + kRegionSlack;
         for (const spgemm_plan_step &stp : P->steps) {
@@ -319,17 +321,22 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
     const double avg_b = B->nrows > 0 ? (double)B->nnz / B->nrows : 1.0;
     int64_t issued_h = 0, issued_d = 0;
     spgemm_status st = SPGEMM_OK;
-    auto h2d = [&](void *dst, const void *src, size_t bytes) {
+    auto h2d_on = [&](hipStream_t st_, void *dst, const void *src, size_t bytes) {
         if (bytes == 0 || e != hipSuccess) return;
-        e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s_h);
+        e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_);
         issued_h += (int64_t)bytes;
     };
+    auto h2d = [&](void *dst, const void *src, size_t bytes) { h2d_on(s_h, dst, src, bytes); };
     auto d2h = [&](void *dst, const void *src, size_t bytes) {
         if (bytes == 0 || e != hipSuccess) return;
         e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s_d);
         issued_d += (int64_t)bytes;
     };
     const bool ac_outer = P->algo != kAlgoChunk2;   // chunk1 and chunkknl keep A/C in place over the B loop
+    // Alg. chunk1: an A/C part's copies in follow the previous part's copy
+    // back on the device-to-host stream (its buffer is free only then), so the
+    // host-to-device stream keeps copying the next B parts meanwhile
+    hipStream_t s_ac = ac_outer ? s_d : s_h;
     int kernels_done = 0;
 
     for (const spgemm_plan_step &stp : P->steps) {
@@ -342,18 +349,20 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
         case kStepH2D:
             if (stp.matrix == kMatA) {
                 AcBuf &b = acb[sac];
-                e = ac_outer ? ev_outer_free.wait(s_h) : ev_d2h[sac].wait(s_h);
+                // chunk1: same stream as the previous part's copy back, which
+                // waited for that part's last kernel
+                if (!ac_outer) e = ev_d2h[sac].wait(s_ac);
                 place_ac(b, A, C, r0, r1);
                 const int64_t a0 = A->row_ptr[r0], a1 = A->row_ptr[r1];
-                h2d(b.arp, A->row_ptr + r0, 4 * (size_t)(r1 - r0 + 1));
-                h2d(b.aci, A->col_idx + a0, 4 * (size_t)(a1 - a0));
-                h2d(b.aval, A->values + a0, 8 * (size_t)(a1 - a0));
+                h2d_on(s_ac, b.arp, A->row_ptr + r0, 4 * (size_t)(r1 - r0 + 1));
+                h2d_on(s_ac, b.aci, A->col_idx + a0, 4 * (size_t)(a1 - a0));
+                h2d_on(s_ac, b.aval, A->values + a0, 8 * (size_t)(a1 - a0));
             } else if (stp.matrix == kMatCStruct) {
                 AcBuf &b = acb[sac];
                 const int64_t c0 = C->row_ptr[r0], c1 = C->row_ptr[r1];
-                h2d(b.crp, C->row_ptr + r0, 4 * (size_t)(r1 - r0 + 1));
-                h2d(b.cci, C->col_idx + c0, 4 * (size_t)(c1 - c0));
-                if (e == hipSuccess) e = ev_ac_ready[sac].record(s_h);
+                h2d_on(s_ac, b.crp, C->row_ptr + r0, 4 * (size_t)(r1 - r0 + 1));
+                h2d_on(s_ac, b.cci, C->col_idx + c0, 4 * (size_t)(c1 - c0));
+                if (e == hipSuccess) e = ev_ac_ready[sac].record(s_ac);
             } else if (stp.matrix == kMatCVal) {
                 AcBuf &b = acb[sac];
                 if (e == hipSuccess) e = ev_last_d2h.wait(s_h);

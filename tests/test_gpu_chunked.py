@@ -33,6 +33,7 @@ CASES = [
     ("stencil", 12, 4.0), ("stencil", 12, 0.5), ("stencil", 12, 0.15), ("stencil", 12, 0.05),
     ("poisson", 0, 3.0), ("poisson", 0, 0.3), ("poisson", 0, 0.08),
     ("rmat", 12, 0.3),   # rows of C past the LDS classes: spill windows on B's row parts
+    ("wide", 0, 0.2),    # B has more rows than A (the shape of R x A)
 ]
 
 
@@ -44,6 +45,9 @@ def case_inputs(kind, n):
         G = synth.rmat_graph(n, 8, seed=5)
         A = synth.Csr(G.nrows, G.ncols, G.row_ptr, G.col_idx, synth.normal_values(len(G.col_idx), 8))
         B = A
+    elif kind == "wide":
+        A = synth.poisson_csr(600, 5000, 12.0, 43)
+        B = synth.poisson_csr(5000, 900, 6.0, 44)
     else:
         A = synth.poisson_csr(3000, 2500, 6.0, 41)
         B = synth.poisson_csr(2500, 2800, 9.0, 42)
@@ -110,7 +114,7 @@ def test_chunked_after_unsynchronised_product_on_same_workspace():
 
 
 @pytest.mark.parametrize("case", [("stencil", 12, 2.0), ("stencil", 12, 0.3), ("stencil", 12, 0.06),
-                                  ("poisson", 0, 0.25), ("rmat", 12, 0.2)])
+                                  ("poisson", 0, 0.25), ("rmat", 12, 0.2), ("wide", 0, 0.2)])
 @pytest.mark.parametrize("nbuf,min_parts", [(1, 1), (2, 3), (4, 1)])
 @pytest.mark.parametrize("ac_where", ["pinned", "hbm"])
 def test_knl_bitwise(case, nbuf, min_parts, ac_where):
