@@ -76,6 +76,28 @@ constexpr int nw_bwd_best(int wave_bytes)
 // B_k) of a staged chunk of A_i are flattened and taken G at a time, one per
 // lane: W_ij is looked up, a_ik W_ij goes to dB with a device atomic and
 // W_ij b_kj to the entry's dA sum in LDS, written out once per entry.
+// Latency: a row's metadata (size, row pointers of W and A) is loaded while
+// the previous row runs, the first chunk of A_i while W_i is hashed, each
+// lane's columns and values of W_i kInsDepth at a time before they are
+// inserted, and the next chunk of A_i while the current one's pairs run.
+constexpr int kBwdInsDepth = 4;
+
+struct BwdMeta {
+    int nw, ws0, ps, pe;
+    bool active;
+};
+
+__device__ __forceinline__ BwdMeta bwd_meta(const Prob &P, const Sched &sc, int g)
+{
+    BwdMeta m{0, 0, 0, 0, g >= 0};
+    if (g < 0) return m;
+    m.nw = gp(sc.val)[g];
+    m.ws0 = gp(P.crp)[g];
+    m.ps = gp(P.arp)[g];
+    m.pe = gp(P.arp)[g + 1];
+    return m;
+}
+
 template <int G, int CAP>
 __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, double *dA, double *dB)
 {
@@ -101,49 +123,61 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
     int *poff = s_poff + rs * (G + 1);
 
     const Prob P = b.p0;
-    const MLS_G int32_t *__restrict__ arp = gp(P.arp);
     const MLS_G int32_t *__restrict__ aci = gp(P.aci);
     const MLS_G double *__restrict__ aval = gp(P.aval);
     const MLS_G int32_t *__restrict__ brp = gp(P.brp);
     const MLS_G int32_t *__restrict__ bci = gp(P.bci);
     const MLS_G double *__restrict__ bval = gp(P.bval);
-    const MLS_G int32_t *__restrict__ wrp = gp(P.crp);
     const MLS_G int32_t *__restrict__ wci = gp(P.cci);
     const MLS_G double *__restrict__ wval = gp(P.cval);
     MLS_G double *__restrict__ gdA = gpw(dA);
-    const MLS_G int32_t *val = gp(sc.val);
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
     TaskIter it = task_iter(ntasks, NW);
-    for (;;) {
-        int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        if (task < 0) break;
-        const int r = task * W + slot;
-        const int gi = r < n_bin ? bin_row(sc.perm, sc.err, b.na, start + r) : -1;
-        const bool active = gi >= 0;
-        const int i = active ? gi : 0;
-        const int nw = active ? val[i] : 0;
+    int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+    int g_cur = -1;
+    if (task >= 0 && task * W + slot < n_bin) g_cur = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
+    BwdMeta m = bwd_meta(P, sc, g_cur);
+    while (task >= 0) {
+        const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
+        const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
+                            ? bin_row(sc.perm, sc.err, b.na, start + task_n * W + slot) : -1;
+        const bool active = m.active;
+        const int nw = m.nw, ws0 = m.ws0, ps = m.ps, pe = m.pe;
         int logcap = ilog2_ceil(2 * nw);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
         const uint32_t cmask = (uint32_t)cap - 1u;
         for (int h = lane; h < cap; h += G) key[h] = -1;
+        // the first chunk of A_i is in flight while W_i is hashed
+        int ka = -1;
+        double sa = 0.0;
+        if (active && ps + lane < pe) { ka = aci[ps + lane]; sa = aval[ps + lane]; }
         bwd_sync();
-        int ps = 0, pe = 0;
         if (active) {
-            const int ws0 = wrp[i];
-            for (int e = lane; e < nw; e += G) {
-                int j = wci[ws0 + e];
-                uint32_t h = hslot((uint32_t)j, logcap);
-                for (uint32_t probe = 0; probe <= cmask; ++probe) {
-                    if (atomicCAS(key + h, -1, j) == -1) { wv[h] = wval[ws0 + e]; break; }
-                    h = (h + 1u) & cmask;
+            for (int e0 = lane; e0 < nw; e0 += G * kBwdInsDepth) {
+                int jv[kBwdInsDepth];
+                double wj[kBwdInsDepth];
+#pragma unroll
+                for (int u = 0; u < kBwdInsDepth; ++u) {
+                    const int e = e0 + u * G;
+                    jv[u] = -1;
+                    wj[u] = 0.0;
+                    if (e < nw) { jv[u] = wci[ws0 + e]; wj[u] = wval[ws0 + e]; }
+                }
+#pragma unroll
+                for (int u = 0; u < kBwdInsDepth; ++u) {
+                    if (jv[u] < 0) continue;
+                    uint32_t h = hslot((uint32_t)jv[u], logcap);
+                    for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                        if (atomicCAS(key + h, -1, jv[u]) == -1) { wv[h] = wj[u]; break; }
+                        h = (h + 1u) & cmask;
+                    }
                 }
             }
-            ps = arp[i];
-            pe = arp[i + 1];
         }
+        m = bwd_meta(P, sc, g_n);   // the next row's metadata, in flight during this row
         bwd_sync();
         bool bad = false;
         // the chunk loop runs to the wave's longest row, so that the group
@@ -153,14 +187,16 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
         for (int c = 0; c < nch; ++c) {
             const int pc = ps + c * G;
             int q0 = 0, np = 0;
-            double a = 0.0;
+            const double a = sa;
             if (pc + lane < pe) {
-                const int k = aci[pc + lane];
-                a = aval[pc + lane];
-                q0 = brp[k];
-                const int q1 = brp[k + 1];
+                q0 = brp[ka];
+                const int q1 = brp[ka + 1];
                 np = q1 > q0 ? q1 - q0 : 0;
             }
+            // the next chunk's entries of A are in flight during this chunk's pairs
+            ka = -1;
+            sa = 0.0;
+            if (pc + G + lane < pe) { ka = aci[pc + G + lane]; sa = aval[pc + G + lane]; }
             int incl = np;
 #pragma unroll
             for (int o = 1; o < G; o <<= 1) {
@@ -208,6 +244,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
         }
         if (bad) atomicOr(sc.err, kErrStructure);
         bwd_sync();
+        task = task_n;
     }
 }
 
@@ -315,12 +352,24 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
             const uint32_t cmask = (uint32_t)cap - 1u;
             for (int h = lane; h < cap; h += G) key[h] = -1;
             bwd_sync();
-            for (int e = lane; e < n; e += G) {
-                const int j = wci[ws0 + e];
-                uint32_t h = hslot((uint32_t)j, logcap);
-                for (uint32_t probe = 0; probe <= cmask; ++probe) {
-                    if (atomicCAS(key + h, -1, j) == -1) { wv[h] = wval[ws0 + e]; break; }
-                    h = (h + 1u) & cmask;
+            for (int e0 = lane; e0 < n; e0 += G * kBwdInsDepth) {
+                int jv[kBwdInsDepth];
+                double wj[kBwdInsDepth];
+#pragma unroll
+                for (int u = 0; u < kBwdInsDepth; ++u) {
+                    const int e = e0 + u * G;
+                    jv[u] = -1;
+                    wj[u] = 0.0;
+                    if (e < n) { jv[u] = wci[ws0 + e]; wj[u] = wval[ws0 + e]; }
+                }
+#pragma unroll
+                for (int u = 0; u < kBwdInsDepth; ++u) {
+                    if (jv[u] < 0) continue;
+                    uint32_t h = hslot((uint32_t)jv[u], logcap);
+                    for (uint32_t probe = 0; probe <= cmask; ++probe) {
+                        if (atomicCAS(key + h, -1, jv[u]) == -1) { wv[h] = wj[u]; break; }
+                        h = (h + 1u) & cmask;
+                    }
                 }
             }
             bwd_sync();

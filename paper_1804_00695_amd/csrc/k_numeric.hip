@@ -129,6 +129,60 @@ struct PosTab {
     }
 };
 
+// Hash a row's columns (column -> position) and set its accumulators (0, or
+// the values already in C when accumulating). Each lane loads D of its
+// columns (then values) before inserting them, so the loads overlap instead
+// of each waiting on the previous insert (D = 2 for 32 or more lanes per
+// row: few columns per lane, and few registers to spare at 8 waves per SIMD).
+template <int G>
+constexpr int ins_depth() { return G >= 32 ? 2 : 4; }
+
+template <int G, int CAP, bool PACK>
+__device__ __forceinline__ void insert_row(PosTab<CAP, PACK> &tab, double *acc, int logcap,
+                                           const MLS_G int32_t *__restrict__ cols,
+                                           const MLS_G double *__restrict__ vals, int off, int n, int lane,
+                                           bool accumulate)
+{
+    constexpr int kInsDepth = ins_depth<G>();
+    if constexpr (kInsDepth == 1) {
+        for (int e = lane; e < n; e += G) {
+            tab.insert(logcap, cols[off + e], e);
+            acc[e] = accumulate ? vals[off + e] : 0.0;
+        }
+        return;
+    }
+    for (int e0 = lane; e0 < n; e0 += G * kInsDepth) {
+        int jv[kInsDepth];
+#pragma unroll
+        for (int u = 0; u < kInsDepth; ++u) {
+            const int e = e0 + u * G;
+            jv[u] = e < n ? cols[off + e] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kInsDepth; ++u)
+            if (jv[u] >= 0) tab.insert(logcap, jv[u], e0 + u * G);
+        if (accumulate) {
+            double v[kInsDepth];
+#pragma unroll
+            for (int u = 0; u < kInsDepth; ++u) {
+                const int e = e0 + u * G;
+                v[u] = e < n ? vals[off + e] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kInsDepth; ++u) {
+                const int e = e0 + u * G;
+                if (e < n) acc[e] = v[u];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kInsDepth; ++u) {
+                const int e = e0 + u * G;
+                if (e < n) acc[e] = 0.0;
+            }
+        }
+    }
+}
+
 constexpr int num_row_bytes(int CAP, int G, bool PACK)
 {
     return CAP * (PACK ? 4 : 8) + (CAP / 2) * 8 + G * 16;
@@ -238,10 +292,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 :
         double sa = 0.0;
         if (ps + lane < pe) { ka = aci[ps + lane]; sa = aval[ps + lane]; }
         nwave_sync();
-        for (int e = lane; e < nc; e += G) {
-            tab.insert(logcap, cci[cs + e], e);
-            acc[e] = accumulate ? cval[cs + e] : 0.0;
-        }
+        insert_row<G, CAP, PACK>(tab, acc, logcap, cci, cval, cs, nc, lane, accumulate);
         m = row_meta<MULTI>(b, sc, act_n, g_n, pc);
         nwave_sync();
         bool bad = false;
@@ -510,10 +561,7 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
             if (logcap < 5) logcap = 5;
             tab.clear(1 << logcap, lane, G);
             nwave_sync();
-            for (int e = lane; e < n; e += G) {
-                tab.insert(logcap, cci[cs + e], e);
-                acc[e] = accumulate ? cval[cs + e] : 0.0;
-            }
+            insert_row<G, CAP, PACK>(tab, acc, logcap, cci, cval, cs, n, lane, accumulate);
             nwave_sync();
             bool bad = false;
             for (int pc = ps; pc < pe; pc += G) {
