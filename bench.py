@@ -499,6 +499,7 @@ def bench_batched(torch, mls, synth, with_parity):
     t_num_call, _ = timed(torch, numeric_per_call, 3)
     prof_rep = profiled(torch, mls, lambda: (mls.batch_numeric(As, Ps, APs, ws), mls.batch_numeric(Rs, APs, Acs, ws)),
                         3)
+    prof_sym = profiled(torch, mls, lambda: (mls.batch_symbolic(As, Ps, ws), mls.batch_symbolic(Rs, APs, ws)), 3)
     replay()   # the outputs checked below are the graph's
     torch.cuda.synchronize()
 
@@ -535,7 +536,9 @@ def bench_batched(torch, mls, synth, with_parity):
                         "frac_replay_AP": frac(model1, t_rep1), "frac_replay_Ac": frac(model2, t_rep2),
                         "numeric_kernels_ms": round(num_kernels_ms, 3),
                         "frac_numeric_kernels": frac(model1 + model2, num_kernels_ms)},
-           "kernels_numeric_stages": kernel_dict(prof_rep, 3)}
+           "kernels_numeric_stages": kernel_dict(prof_rep, 3),
+           "symbolic_stages_kernels_ms": round(kernels_ms(prof_sym, 3, ("",)), 3),
+           "kernels_symbolic_stages": kernel_dict(prof_sym, 3)}
     ok = None
     if with_parity:
         import oracle

@@ -86,10 +86,22 @@ class DeviceCsr:
     def nnz(self) -> int:
         return int(self.col_idx.numel())
 
+    def __setattr__(self, name, value):
+        # any change of a field drops the checked handle
+        object.__setattr__(self, name, value)
+        if name != "_handle":
+            object.__setattr__(self, "_handle", None)
+
     def handle(self) -> CsrT:
-        """C handle; checks dtypes, device, contiguity and lengths first."""
-        _check_csr(self, "cuda")
-        return CsrT(self.nrows, self.ncols, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.values))
+        """C handle; checks dtypes, device, contiguity and lengths the first
+        time (and again after a field is reassigned). Tensors resized in place
+        after that are not seen: build a new DeviceCsr instead."""
+        h = self.__dict__.get("_handle")
+        if h is None:
+            _check_csr(self, "cuda")
+            h = CsrT(self.nrows, self.ncols, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.values))
+            object.__setattr__(self, "_handle", h)
+        return h
 
     @classmethod
     def from_host(cls, M, device="cuda", values: bool = True) -> "DeviceCsr":

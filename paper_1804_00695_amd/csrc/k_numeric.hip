@@ -31,7 +31,7 @@
 
 namespace mls {
 
-constexpr int kNumDepth = 4;   // steps whose B loads are issued together
+constexpr int kNumDepth = 4;   // steps whose B loads are issued together (8 where LDS caps occupancy at 4)
 constexpr int kNumWinCap = 1024;   // table slots of a spill window (CAP / 2 positions)
 constexpr int kWinDepth = 2;
 constexpr bool kNumFlat = true;    // flattened pairs for the classes of at most kNumFlatMaxG lanes per row
@@ -229,9 +229,32 @@ __device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, boo
 // lane marks and the staged pair offsets follow the tables in LDS.
 constexpr int num_flat_words(int CAP, int G) { return CAP / 2 + G + 1; }
 
-template <int G, int CAP, bool PACK, bool MULTI, bool FLAT>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(MULTI ? 5 : 8))) void k_num_lds(Batch b, Sched sc, int bin)
+// Waves per SIMD that the LDS of one workgroup (NW waves) leaves resident:
+// 160 KB per CU, 4 SIMDs, at most 8 waves each.
+constexpr int lds_waves_per_simd(int wg_bytes, int nw)
 {
+    int wgs = 163840 / wg_bytes;
+    int w = wgs * nw / 4;
+    return w > 8 ? 8 : (w < 1 ? 1 : w);
+}
+
+template <int G, int CAP, bool PACK, bool FLAT>
+struct NumShape {
+    static constexpr int W = kWave / G;
+    static constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
+    static constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
+    static constexpr int OCC = lds_waves_per_simd(NW * W * (num_row_bytes(CAP, G, PACK) + 4 * XW), NW);
+    // where LDS already limits a SIMD to 4 waves, registers are free for
+    // twice the steps in flight
+    static constexpr int DEPTH = OCC <= 4 ? 2 * kNumDepth : kNumDepth;
+};
+
+template <int G, int CAP, bool PACK, bool MULTI, bool FLAT>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
+    MULTI ? (NumShape<G, CAP, PACK, FLAT>::OCC < 5 ? NumShape<G, CAP, PACK, FLAT>::OCC : 5)
+          : NumShape<G, CAP, PACK, FLAT>::OCC))) void k_num_lds(Batch b, Sched sc, int bin)
+{
+    constexpr int kNumDepth = NumShape<G, CAP, PACK, FLAT>::DEPTH;
     constexpr int W = kWave / G;
     constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
     constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
@@ -658,10 +681,9 @@ static int persistent_grid_n(K kernel, int threads)
     return cus * per_cu;
 }
 
-template <int G, int CAP, bool PACK, bool MULTI>
+template <int G, int CAP, bool PACK, bool MULTI, bool FLAT>
 static void launch_num_variant(const Batch &b, const Sched &sc, int bin, hipStream_t s)
 {
-    constexpr bool FLAT = kNumFlat && G <= kNumFlatMaxG;
     constexpr int W = kWave / G;
     constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
     constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
@@ -676,8 +698,9 @@ static void launch_num_variant(const Batch &b, const Sched &sc, int bin, hipStre
 template <int G, int CAP, bool PACK>
 static void launch_num_multi(const Batch &b, const Sched &sc, int bin, hipStream_t s)
 {
-    if (b.nprob > 1) launch_num_variant<G, CAP, PACK, true>(b, sc, bin, s);
-    else launch_num_variant<G, CAP, PACK, false>(b, sc, bin, s);
+    constexpr bool FLAT = kNumFlat && G <= kNumFlatMaxG;
+    if (b.nprob > 1) launch_num_variant<G, CAP, PACK, true, FLAT>(b, sc, bin, s);
+    else launch_num_variant<G, CAP, PACK, false, FLAT>(b, sc, bin, s);
 }
 
 // The packed table needs every column index below PackBits<CAP>::kMaxCols.
