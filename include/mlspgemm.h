@@ -316,6 +316,27 @@ spgemm_status spgemm_numeric_chunked(const spgemm_csr *A_host, const spgemm_csr 
                                      spgemm_csr *C_host, spgemm_plan *plan, void *ws, size_t ws_bytes,
                                      hipStream_t s_compute, hipStream_t s_h2d, hipStream_t s_d2h);
 
+/* Test support: what spgemm_numeric_chunked would queue for this plan and
+ * these host operands, recorded instead of queued (no GPU call; nothing is
+ * read but the host row pointers, nothing is written but out). Each entry is
+ * one access of one operation, in issue order: op numbers the operation;
+ * kind 0 copy host->device, 1 copy device->host, 2 kernel (the first
+ * operation, kernel on the whole workspace, stands for work queued earlier
+ * on the compute stream), 3 fill, 4 event record, 5 event wait; stream 0
+ * compute, 1 host->device, 2 device->host; event (record / wait) an id, else
+ * -1; space 0 the workspace, 1 C's values in host memory, -1 none; write 1
+ * for a write, 0 for a read; [lo, hi) the byte range in that space. A
+ * checker can derive the happens-before order from stream order and the
+ * events and verify that conflicting accesses are ordered. *n_entries
+ * receives the count; at most max_entries are copied. */
+typedef struct {
+    int32_t op, kind, stream, event, space, write;
+    int64_t lo, hi;
+} spgemm_trace_entry;
+spgemm_status spgemm_numeric_chunked_trace(const spgemm_csr *A_host, const spgemm_csr *B_host,
+                                           const spgemm_csr *C_host, spgemm_plan *plan, spgemm_trace_entry *out,
+                                           int64_t max_entries, int64_t *n_entries);
+
 /* ------------------------------------------------------------------------
  * Triangle counting (Sec. 4.1.2)
  * --------------------------------------------------------------------- */

@@ -387,6 +387,30 @@ def numeric_chunked(A, B, C, plan: Plan, ws: Optional[Workspace] = None,
     return C
 
 
+def chunked_trace(A, B, C, plan: Plan):
+    """The operations spgemm_numeric_chunked would queue (recorded, not run;
+    no GPU needed). A, B, C: host CSR with numpy arrays (C's values array is
+    only used as the base of its host byte ranges). Returns a list of
+    (op, kind, stream, event, space, write, lo, hi) tuples."""
+    keep = []
+
+    def host(M, values=True):
+        rp = np.ascontiguousarray(M.row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(M.col_idx, dtype=np.int32)
+        v = np.ascontiguousarray(M.values if M.values is not None else np.zeros(len(ci)), dtype=np.float64)
+        keep.append((rp, ci, v))
+        return CsrT(int(M.nrows), int(M.ncols), int(rp[-1]), rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                    v.ctypes.data if v.size else None)
+    ha, hb, hc = host(A), host(B), host(C)
+    n = ctypes.c_int64(0)
+    check(lib.spgemm_numeric_chunked_trace(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(hc), plan._h, None, 0,
+                                           ctypes.byref(n)), "spgemm_numeric_chunked_trace")
+    arr = (_abi.TraceEntry * max(n.value, 1))()
+    check(lib.spgemm_numeric_chunked_trace(ctypes.byref(ha), ctypes.byref(hb), ctypes.byref(hc), plan._h, arr,
+                                           n.value, ctypes.byref(n)), "spgemm_numeric_chunked_trace")
+    return [(t.op, t.kind, t.stream, t.event, t.space, t.write, t.lo, t.hi) for t in arr[:n.value]]
+
+
 # ---------------------------------------------------------------------------
 # triangle counting
 

@@ -29,6 +29,11 @@ class PlanStep(ctypes.Structure):
                 ("row_end", c_int32), ("slot", c_int32), ("bytes", c_int64)]
 
 
+class TraceEntry(ctypes.Structure):
+    _fields_ = [("op", c_int32), ("kind", c_int32), ("stream", c_int32), ("event", c_int32), ("space", c_int32),
+                ("write", c_int32), ("lo", c_int64), ("hi", c_int64)]
+
+
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 64), ("calls", c_int64), ("total_ms", ctypes.c_double)]
 
@@ -63,6 +68,7 @@ SIGNATURES = {
     "spgemm_plan_steps": (ctypes.c_int, [P, ctypes.POINTER(PlanStep), c_int32]),
     "spgemm_plan_destroy": (None, [P]),
     "spgemm_numeric_chunked": (ctypes.c_int, [CSRP, CSRP, CSRP, P, P, c_size_t, P, P, P]),
+    "spgemm_numeric_chunked_trace": (ctypes.c_int, [CSRP, CSRP, CSRP, P, ctypes.POINTER(TraceEntry), c_int64, I64P]),
     "spgemm_tc_lower": (ctypes.c_int, [CSRP, P, P, P, I64P]),
     "spgemm_tc_workspace_size": (ctypes.c_int, [CSRP, SZP]),
     "spgemm_tc": (ctypes.c_int, [CSRP, P, I64P, P, c_size_t, P]),

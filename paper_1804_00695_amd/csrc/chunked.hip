@@ -54,15 +54,59 @@ struct BBuf {
     double *bval = nullptr;
 };
 
+// Records, instead of queueing, what a chunked run would queue: every copy,
+// fill and kernel with the byte ranges it reads and writes, and every event
+// record and wait, with the stream each goes to (test support; nothing is
+// touched but the host row pointers).
+enum { kTrH2D = 0, kTrD2H = 1, kTrKernel = 2, kTrFill = 3, kTrRecord = 4, kTrWait = 5 };
+enum { kSpaceWs = 0, kSpaceHostCVal = 1 };
+
+struct Tracer {
+    std::vector<spgemm_trace_entry> v;
+    const char *ws = nullptr;
+    const double *host_cval = nullptr;
+    hipStream_t sc = nullptr, sh = nullptr, sd = nullptr;
+    int op = 0;
+    int sid(hipStream_t s) const { return s == sc ? 0 : (s == sh ? 1 : 2); }
+    void begin() { ++op; }
+    void access(int kind, hipStream_t s, int space, int write, int64_t lo, int64_t hi)
+    {
+        spgemm_trace_entry t;
+        t.op = op; t.kind = kind; t.stream = sid(s); t.event = -1; t.space = space; t.write = write;
+        t.lo = lo; t.hi = hi;
+        v.push_back(t);
+    }
+    void ws_range(int kind, hipStream_t s, int write, const void *p, size_t bytes)
+    {
+        const int64_t lo = (const char *)p - ws;
+        access(kind, s, kSpaceWs, write, lo, lo + (int64_t)bytes);
+    }
+    void event(int kind, hipStream_t s, int id)
+    {
+        begin();
+        spgemm_trace_entry t;
+        t.op = op; t.kind = kind; t.stream = sid(s); t.event = id; t.space = -1; t.write = 0; t.lo = t.hi = 0;
+        v.push_back(t);
+    }
+};
+
 struct Ev {
     hipEvent_t e = nullptr;
     bool recorded = false;
+    int id = -1;
+    Tracer *tr = nullptr;
     hipError_t record(hipStream_t s)
     {
         recorded = true;
+        if (tr) { tr->event(kTrRecord, s, id); return hipSuccess; }
         return hipEventRecord(e, s);
     }
-    hipError_t wait(hipStream_t s) const { return recorded ? hipStreamWaitEvent(s, e, 0) : hipSuccess; }
+    hipError_t wait(hipStream_t s) const
+    {
+        if (!recorded) return hipSuccess;
+        if (tr) { tr->event(kTrWait, s, id); return hipSuccess; }
+        return hipStreamWaitEvent(s, e, 0);
+    }
 };
 
 // Bytes an A/C part [r0, r1) occupies in its buffer (each array on a
@@ -183,9 +227,10 @@ spgemm_status numeric_launch(const Batch &b, double avg_b, char *ws, const Layou
 
 }  // namespace mls
 
-extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgemm_csr *B, spgemm_csr *C,
-                                                spgemm_plan *plan, void *ws_v, size_t ws_bytes, hipStream_t s_c,
-                                                hipStream_t s_h, hipStream_t s_d)
+namespace {
+
+spgemm_status run_chunked(const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *C, spgemm_plan *plan,
+                          void *ws_v, size_t ws_bytes, hipStream_t s_c, hipStream_t s_h, hipStream_t s_d, Tracer *tr)
 {
     if (!A || !B || !C || !plan || !ws_v) return SPGEMM_ERR_INVALID_ARG;
     PlanImpl *P = reinterpret_cast<PlanImpl *>(plan);
@@ -224,19 +269,20 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
             if (stp.matrix == kMatB && b_extent(B, stp.row_begin, stp.row_end) > rb0) return SPGEMM_ERR_DIM_MISMATCH;
         }
     }
-    int dev = 0;
-    {
-        hipError_t ed = hipGetDevice(&dev);
-        if (ed != hipSuccess) return hip_fail(ed);
-    }
     // B (and, except under chunkknl, A and C) are copied from and to
-    // page-locked host memory; chunkknl's kernels use A and C in place
+    // page-locked host memory; chunkknl's kernels use A and C in place. A
+    // trace takes them as they are.
     spgemm_csr Ad = *A, Cd = *C;
     bool a_host = true, c_host = true;
-    spgemm_status sv = pinned_csr(*B, dev);
-    if (sv == SPGEMM_OK) sv = knl ? device_csr(Ad, dev, &a_host) : pinned_csr(*A, dev);
-    if (sv == SPGEMM_OK) sv = knl ? device_csr(Cd, dev, &c_host) : pinned_csr(*C, dev);
-    if (sv != SPGEMM_OK) return sv;
+    if (!tr) {
+        int dev = 0;
+        hipError_t ed = hipGetDevice(&dev);
+        if (ed != hipSuccess) return hip_fail(ed);
+        spgemm_status sv = pinned_csr(*B, dev);
+        if (sv == SPGEMM_OK) sv = knl ? device_csr(Ad, dev, &a_host) : pinned_csr(*A, dev);
+        if (sv == SPGEMM_OK) sv = knl ? device_csr(Cd, dev, &c_host) : pinned_csr(*C, dev);
+        if (sv != SPGEMM_OK) return sv;
+    }
     // chunkknl: B's row pointers, and those of A and C when they are in host
     // memory, must be consistent; A and C in device memory are used as they
     // are, like spgemm_numeric's operands
@@ -249,7 +295,7 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
                 (stp.kind == kStepH2D && b_extent(B, stp.row_begin, stp.row_end) > al((size_t)P->max_b) + kRegionSlack))
                 return SPGEMM_ERR_DIM_MISMATCH;
     char *ws = (char *)ws_v;
-    memo_forget(ws_v);
+    if (!tr) memo_forget(ws_v);
 
     const Layout L = make_layout(1, A->nrows, B->nrows, 0, B->ncols, false);
     int32_t *bin_tbl = (int32_t *)(ws + al(L.total));
@@ -297,39 +343,72 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
         all.push_back(&ev_d2h[s]);
     }
     hipError_t e = hipSuccess;
-    for (Ev *x : all)
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&x->e, hipEventDisableTiming);
+    for (size_t k = 0; k < all.size(); ++k) {
+        all[k]->id = (int)k + 1;
+        all[k]->tr = tr;
+        if (!tr && e == hipSuccess) e = hipEventCreateWithFlags(&all[k]->e, hipEventDisableTiming);
+    }
     auto cleanup = [&]() {
         for (Ev *x : all)
             if (x->e) hipEventDestroy(x->e);
     };
     if (e != hipSuccess) { cleanup(); return hip_fail(e); }
+    // the kernels' own region (header, per-row arrays, kept binnings), which
+    // only work on the compute stream touches
+    const size_t kern_bytes = (size_t)(buf0 - ws);
+    if (tr) {   // work queued earlier on the compute stream may use all of the workspace
+        tr->begin();
+        tr->ws_range(kTrKernel, s_c, 1, ws, ws_bytes);
+    }
     // the copy streams must not overwrite the workspace while work queued
     // earlier on the compute stream (an in-HBM product on the same
     // workspace, for instance) still reads it
     {
         Ev entry;
-        e = hipEventCreateWithFlags(&entry.e, hipEventDisableTiming);
+        entry.tr = tr;
+        if (!tr) e = hipEventCreateWithFlags(&entry.e, hipEventDisableTiming);
         if (e == hipSuccess) e = entry.record(s_c);
         if (e == hipSuccess) e = entry.wait(s_h);
         if (e == hipSuccess) e = entry.wait(s_d);
         if (entry.e) hipEventDestroy(entry.e);
         if (e != hipSuccess) { cleanup(); return hip_fail(e); }
     }
-    reset_header(ws, L, s_c);
+    if (tr) {
+        tr->begin();
+        tr->ws_range(kTrFill, s_c, 1, ws, kern_bytes);
+    } else {
+        reset_header(ws, L, s_c);
+    }
 
     const double avg_b = B->nrows > 0 ? (double)B->nnz / B->nrows : 1.0;
     int64_t issued_h = 0, issued_d = 0;
     spgemm_status st = SPGEMM_OK;
     auto h2d_on = [&](hipStream_t st_, void *dst, const void *src, size_t bytes) {
         if (bytes == 0 || e != hipSuccess) return;
-        e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_);
+        if (tr) {
+            tr->begin();
+            tr->ws_range(kTrH2D, st_, 1, dst, bytes);
+            const char *hc = (const char *)tr->host_cval;
+            if ((const char *)src >= hc && (const char *)src < hc + 8 * (size_t)C->nnz) {
+                const int64_t lo = (const char *)src - hc;
+                tr->access(kTrH2D, st_, kSpaceHostCVal, 0, lo, lo + (int64_t)bytes);
+            }
+        } else {
+            e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st_);
+        }
         issued_h += (int64_t)bytes;
     };
     auto h2d = [&](void *dst, const void *src, size_t bytes) { h2d_on(s_h, dst, src, bytes); };
-    auto d2h = [&](void *dst, const void *src, size_t bytes) {
+    auto d2h = [&](double *dst, const void *src, size_t bytes) {
         if (bytes == 0 || e != hipSuccess) return;
-        e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s_d);
+        if (tr) {
+            tr->begin();
+            tr->ws_range(kTrD2H, s_d, 0, src, bytes);
+            const int64_t lo = (const char *)dst - (const char *)tr->host_cval;
+            tr->access(kTrD2H, s_d, kSpaceHostCVal, 1, lo, lo + (int64_t)bytes);
+        } else {
+            e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s_d);
+        }
         issued_d += (int64_t)bytes;
     };
     const bool ac_outer = P->algo != kAlgoChunk2;   // chunk1 and chunkknl keep A/C in place over the B loop
@@ -384,7 +463,12 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
             AcBuf &b = acb[sac];
             e = ac_outer ? ev_outer_free.wait(s_c) : ev_d2h[sac].wait(s_c);
             const int64_t nc = (int64_t)C->row_ptr[r1] - C->row_ptr[r0];
-            if (e == hipSuccess) launch_fill_f64(b.cval, 0.0, nc, s_c);
+            if (e == hipSuccess && tr) {
+                tr->begin();
+                tr->ws_range(kTrFill, s_c, 1, b.cval, 8 * (size_t)nc);
+            } else if (e == hipSuccess) {
+                launch_fill_f64(b.cval, 0.0, nc, s_c);
+            }
             break;
         }
         case kStepKernel: {
@@ -427,7 +511,20 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
             q.k_lo = bq.r0;
             q.k_hi = bq.r1;
             const bool first = !binned[stp.part];
-            st = numeric_launch(bt, avg_b, ws, L, bin_tbl, keep, stp.part, a_r0, first, s_c);
+            if (tr) {
+                tr->begin();
+                tr->ws_range(kTrKernel, s_c, 1, ws, kern_bytes);
+                tr->ws_range(kTrKernel, s_c, 0, bq.base, (size_t)((const char *)(bq.bval + (B->row_ptr[bq.r1] - B->row_ptr[bq.r0])) - bq.base));
+                if (knl) {   // C's values rewritten in place in host memory
+                    tr->access(kTrKernel, s_c, kSpaceHostCVal, 1, 0, 8 * C->nnz);
+                } else {
+                    AcBuf &a = acb[sac];
+                    tr->ws_range(kTrKernel, s_c, 0, a.base, (size_t)((const char *)a.cval - a.base));
+                    tr->ws_range(kTrKernel, s_c, 1, a.cval, 8 * (size_t)a.nnz_c);
+                }
+            } else {
+                st = numeric_launch(bt, avg_b, ws, L, bin_tbl, keep, stp.part, a_r0, first, s_c);
+            }
             binned[stp.part] = 1;
             ++kernels_done;
             if (st == SPGEMM_OK) e = ev_kdone[ac_outer ? sb : sac].record(s_c);
@@ -446,6 +543,7 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
         }
         }
     }
+    if (tr) return e == hipSuccess ? st : hip_fail(e);
     hipError_t e2 = hipStreamSynchronize(s_c);
     hipError_t e3 = hipStreamSynchronize(s_h);
     hipError_t e4 = hipStreamSynchronize(s_d);
@@ -459,4 +557,37 @@ extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgem
     if (st != SPGEMM_OK) return st;
     // structure errors flagged by the kernels
     return read_errors(ws, L, s_c);
+}
+
+}  // namespace
+
+extern "C" spgemm_status spgemm_numeric_chunked(const spgemm_csr *A, const spgemm_csr *B, spgemm_csr *C,
+                                                spgemm_plan *plan, void *ws_v, size_t ws_bytes, hipStream_t s_c,
+                                                hipStream_t s_h, hipStream_t s_d)
+{
+    return run_chunked(A, B, C, plan, ws_v, ws_bytes, s_c, s_h, s_d, nullptr);
+}
+
+extern "C" spgemm_status spgemm_numeric_chunked_trace(const spgemm_csr *A, const spgemm_csr *B, const spgemm_csr *C,
+                                                      spgemm_plan *plan, spgemm_trace_entry *out,
+                                                      int64_t max_entries, int64_t *n_entries)
+{
+    if (!plan || !n_entries || !C || (max_entries > 0 && !out)) return SPGEMM_ERR_INVALID_ARG;
+    PlanImpl *P = reinterpret_cast<PlanImpl *>(plan);
+    Tracer tr;
+    // a stand-in workspace base: ranges are reported relative to it and
+    // nothing at it is ever read or written
+    tr.ws = reinterpret_cast<const char *>((uintptr_t)1 << 20);
+    tr.host_cval = C->values;
+    tr.sc = reinterpret_cast<hipStream_t>((uintptr_t)0x10);
+    tr.sh = reinterpret_cast<hipStream_t>((uintptr_t)0x20);
+    tr.sd = reinterpret_cast<hipStream_t>((uintptr_t)0x30);
+    const int64_t saved_h = P->issued_h2d, saved_d = P->issued_d2h;
+    spgemm_status st = run_chunked(A, B, C, plan, (void *)tr.ws, (size_t)P->ws_bytes, tr.sc, tr.sh, tr.sd, &tr);
+    P->issued_h2d = saved_h;
+    P->issued_d2h = saved_d;
+    if (st != SPGEMM_OK) return st;
+    *n_entries = (int64_t)tr.v.size();
+    for (int64_t k = 0; k < max_entries && k < (int64_t)tr.v.size(); ++k) out[k] = tr.v[(size_t)k];
+    return SPGEMM_OK;
 }
