@@ -526,7 +526,7 @@ def bench_batched(torch, mls, synth, with_parity):
                         "replay_AP": round(t_rep1, 3), "replay_Ac": round(t_rep2, 3)},
            "numeric_per_call_ms": round(t_num_call, 2), "numeric_graph_replay_ms": round(t_replay, 3),
            "speedup_replay_vs_numeric_per_call": round(t_num_call / t_replay, 2),
-           "autotuned_group_size": [plan1.group_size, plan2.group_size],
+           "autotuned_schedule_g1_g2_floor": [plan1.schedule, plan2.schedule],
            "replay_gflops": round(2.0 * madds / (t_replay * 1e-3) / 1e9, 1),
            "roofline": {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "bytes_model": "numeric byte model summed over the 512 products",

@@ -379,15 +379,31 @@ spgemm_status spgemm_batch_numeric(int32_t nbatch, const spgemm_csr *A, const sp
  * reuse): the row binning is done once, the launches are captured into a
  * HIP graph, and spgemm_batch_plan_run replays them. The plan keeps
  * pointers to the caller's arrays and its part of the workspace; both must
- * stay valid until spgemm_batch_plan_destroy. group_size 0 = heuristic. */
+ * stay valid until spgemm_batch_plan_destroy.
+ * group_size 8/16/32/64: lanes per row of the first LDS class, rows binned by
+ * size. group_size 0: autotuned -- every combination of the lanes per row of
+ * the first LDS class (8, 16, 32, 64), of the second (32, 64), and of the
+ * row-bin threshold between the two smallest classes (rows binned by size,
+ * or every row of the smallest class moved up to the next) is timed on the
+ * batch with HIP events and the fastest kept; all give identical results.
+ * The choice is cached in the process by the batch's shape, and, when
+ * tune_cache_path is not NULL, read from and appended to that text file
+ * (lines "batch <nbatch> <rows of A> <rows of B> <nnz A> <nnz C> <device>
+ * <g1> <g2> <floor>"; unreadable lines are ignored), so that other processes
+ * on the same kind of GPU skip the search. Tuning synchronises the stream. */
 typedef struct spgemm_batch_plan spgemm_batch_plan;
 spgemm_status spgemm_batch_plan_create(int32_t nbatch, const spgemm_csr *A, const spgemm_csr *B,
-                                       spgemm_csr *C, int32_t group_size, int32_t use_graph, void *ws,
-                                       size_t ws_bytes, hipStream_t stream, spgemm_batch_plan **out);
+                                       spgemm_csr *C, int32_t group_size, int32_t use_graph,
+                                       const char *tune_cache_path, void *ws, size_t ws_bytes,
+                                       hipStream_t stream, spgemm_batch_plan **out);
 spgemm_status spgemm_batch_plan_run(spgemm_batch_plan *plan, hipStream_t stream);
 /* Lanes per row the plan uses for its first LDS class (the autotuned value
  * when created with group_size 0). */
 int32_t spgemm_batch_plan_group_size(const spgemm_batch_plan *plan);
+/* The plan's whole schedule: lanes per row of the first and second LDS
+ * classes and the row-bin floor (-1: rows binned by size; 1: the smallest
+ * class's rows moved up to the next). */
+spgemm_status spgemm_batch_plan_schedule(const spgemm_batch_plan *plan, int32_t *g1, int32_t *g2, int32_t *floor);
 void spgemm_batch_plan_destroy(spgemm_batch_plan *plan);
 
 /* ------------------------------------------------------------------------

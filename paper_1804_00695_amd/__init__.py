@@ -637,21 +637,30 @@ class BatchPlan:
 
     Owns its own workspace: the binning lives there between runs."""
 
-    def __init__(self, As, Bs, Cs, group_size: int = 0, use_graph: bool = True):
+    def __init__(self, As, Bs, Cs, group_size: int = 0, use_graph: bool = True, tune_cache: Optional[str] = None):
         dev = As[0].row_ptr.device
         self.ws = Workspace(dev)
         self._destroy = lib.spgemm_batch_plan_destroy   # still bound at interpreter exit
         nb = batch_workspace_size(As, Bs)
         self._keep = (As, Bs, Cs, _handles(As), _handles(Bs), _handles(Cs))
         out = ctypes.c_void_p(0)
+        path = None if tune_cache is None else str(tune_cache).encode()
         check(lib.spgemm_batch_plan_create(len(As), self._keep[3], self._keep[4], self._keep[5], group_size,
-                                           1 if use_graph else 0, self.ws.get(nb), nb, stream_handle(),
+                                           1 if use_graph else 0, path, self.ws.get(nb), nb, stream_handle(),
                                            ctypes.byref(out)), "spgemm_batch_plan_create")
         self._h = out.value
 
     @property
     def group_size(self) -> int:
         return lib.spgemm_batch_plan_group_size(self._h)
+
+    @property
+    def schedule(self):
+        """(lanes per row of the first LDS class, of the second, row-bin floor)."""
+        g1, g2, fl = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        check(lib.spgemm_batch_plan_schedule(self._h, ctypes.byref(g1), ctypes.byref(g2), ctypes.byref(fl)),
+              "spgemm_batch_plan_schedule")
+        return g1.value, g2.value, fl.value
 
     def run(self):
         check(lib.spgemm_batch_plan_run(self._h, stream_handle()), "spgemm_batch_plan_run")

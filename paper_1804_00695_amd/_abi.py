@@ -75,8 +75,10 @@ SIGNATURES = {
     "spgemm_batch_workspace_size": (ctypes.c_int, [c_int32, CSRP, CSRP, SZP]),
     "spgemm_batch_symbolic": (ctypes.c_int, [c_int32, CSRP, CSRP, CSRP, c_int32, I64P, P, c_size_t, P]),
     "spgemm_batch_numeric": (ctypes.c_int, [c_int32, CSRP, CSRP, CSRP, P, c_size_t, P]),
-    "spgemm_batch_plan_create": (ctypes.c_int, [c_int32, CSRP, CSRP, CSRP, c_int32, c_int32, P, c_size_t, P,
-                                                ctypes.POINTER(P)]),
+    "spgemm_batch_plan_create": (ctypes.c_int, [c_int32, CSRP, CSRP, CSRP, c_int32, c_int32, ctypes.c_char_p, P,
+                                                c_size_t, P, ctypes.POINTER(P)]),
+    "spgemm_batch_plan_schedule": (ctypes.c_int, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                                                  ctypes.POINTER(c_int32)]),
     "spgemm_batch_plan_run": (ctypes.c_int, [P, P]),
     "spgemm_batch_plan_group_size": (c_int32, [P]),
     "spgemm_batch_plan_destroy": (None, [P]),

@@ -738,21 +738,26 @@ static void launch_num_spill(const Batch &b, const Sched &sc, hipStream_t s)
     }
 }
 
-void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s)
+void launch_numeric_groups(const Batch &b, const Sched &sc, int G1, int G2, hipStream_t s)
 {
     if (b.na <= 0) return;
     launch_num_class<8, kFillCap[0]>(b, sc, 0, s);
-    switch (G) {
+    switch (G1) {
     case 8: launch_num_class<8, kFillCap[1]>(b, sc, 1, s); break;
     case 16: launch_num_class<16, kFillCap[1]>(b, sc, 1, s); break;
     case 64: launch_num_class<64, kFillCap[1]>(b, sc, 1, s); break;
     default: launch_num_class<32, kFillCap[1]>(b, sc, 1, s); break;
     }
-    if (G >= 64) launch_num_class<64, kFillCap[2]>(b, sc, 2, s);
+    if (G2 >= 64) launch_num_class<64, kFillCap[2]>(b, sc, 2, s);
     else launch_num_class<32, kFillCap[2]>(b, sc, 2, s);
     launch_num_class<64, kFillCap[3]>(b, sc, 3, s);
     launch_num_class<64, kFillCap[4]>(b, sc, 4, s);
     launch_num_spill(b, sc, s);
+}
+
+void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s)
+{
+    launch_numeric_groups(b, sc, G, G >= 64 ? 64 : 32, s);
 }
 
 }  // namespace mls

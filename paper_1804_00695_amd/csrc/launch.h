@@ -33,6 +33,8 @@ __global__ void k_win_scan(Batch b, Sched sc, int m);
 
 // Numeric phase (row-range fused multiply-add) over the binned rows.
 void launch_numeric(const Batch &b, const Sched &sc, int G, hipStream_t s);
+// The same with the lanes per row of the first (G1) and second (G2) LDS classes given.
+void launch_numeric_groups(const Batch &b, const Sched &sc, int G1, int G2, hipStream_t s);
 
 // Triangle counting over the binned rows of L (A = B = L in the batch).
 void launch_tc(const Batch &b, const Sched &sc, int64_t *counts, unsigned long long *total,

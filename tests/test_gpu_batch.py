@@ -113,3 +113,40 @@ def test_batch_with_spill_rows():
         torch.cuda.synchronize()
         plan.run()
         check_all(prods, Cs)
+
+
+def test_tuned_schedule_persisted_and_reused(tmp_path):
+    """The autotuner writes its choice to the cache file; a plan for another
+    batch shape whose line is already in the file takes that schedule without
+    searching (the crafted schedule moves the smallest class's rows up and
+    uses 64 lanes in both classes), and its results stay bit-exact."""
+    cache = tmp_path / "tune.txt"
+    prods = mixed_batch()
+    As, Bs = to_dev(prods)
+    Cs = mls.batch_symbolic(As, Bs)
+    plan = mls.BatchPlan(As, Bs, Cs, use_graph=True, tune_cache=cache)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("batch ")
+    f = lines[0].split()
+    g1, g2, fl = plan.schedule
+    assert (int(f[7]), int(f[8]), int(f[9])) == (g1, g2, fl)
+    plan.run()
+    check_all(prods, Cs)
+    # a second shape: its line is written by hand with the first line's device
+    prods2 = prods[:-2]
+    As2, Bs2 = to_dev(prods2)
+    Cs2 = mls.batch_symbolic(As2, Bs2)
+    na = sum(a.nrows for a, _ in prods2)
+    nb = sum(b.nrows for _, b in prods2)
+    za = sum(a.nnz for a, _ in prods2)
+    zc = sum(c.nnz for c in Cs2)
+    with open(cache, "a") as fh:
+        fh.write("not a schedule line\n")
+        fh.write(f"batch {len(prods2)} {na} {nb} {za} {zc} {f[6]} 64 64 1\n")
+    plan2 = mls.BatchPlan(As2, Bs2, Cs2, use_graph=True, tune_cache=cache)
+    assert plan2.schedule == (64, 64, 1)
+    assert len(cache.read_text().splitlines()) == 3      # nothing appended: no search
+    for C in Cs2:
+        C.values.fill_(float("nan"))
+    plan2.run()
+    check_all(prods2, Cs2)
