@@ -83,17 +83,34 @@ struct PosTab {
         }
     }
 
+    static constexpr uint32_t kEmpty = 0xffffffffu;
+
+    // Packed tables are probed a bucket (4 slots, 16 bytes) at a time: a key
+    // takes the first empty slot at or after the start of its home bucket, so
+    // the filled slots of every bucket are a prefix of it (a lane only claims
+    // a slot after seeing every earlier one taken, and slots are never
+    // emptied), and a bucket whose last slot is empty ends a search.
+    __device__ __forceinline__ static uint32_t home(int logcap, int j)
+    {
+        return hslot((uint32_t)j, logcap - 2) << 2;
+    }
+    __device__ __forceinline__ uint4 bucket(uint32_t h) const { return *(const uint4 *)(t + h); }
+
     __device__ __forceinline__ void insert(int logcap, int j, int pos)
     {
         const uint32_t cmask = (1u << logcap) - 1u;
-        uint32_t h = hslot((uint32_t)j, logcap);
         if (PACK) {
             const uint32_t v = ((uint32_t)j << PackBits<CAP>::PB) | (uint32_t)pos;
-            for (uint32_t probe = 0; probe <= cmask; ++probe) {
-                if (atomicCAS(t + h, 0xffffffffu, v) == 0xffffffffu) return;
-                h = (h + 1u) & cmask;
+            uint32_t h = home(logcap, j);
+            for (uint32_t probe = 0; probe <= cmask; probe += 4) {
+                const uint4 w = bucket(h);
+                int sl = w.x == kEmpty ? 0 : (w.y == kEmpty ? 1 : (w.z == kEmpty ? 2 : (w.w == kEmpty ? 3 : 4)));
+                for (; sl < 4; ++sl)
+                    if (atomicCAS(t + h + sl, kEmpty, v) == kEmpty) return;
+                h = (h + 4u) & cmask;
             }
         } else {
+            uint32_t h = hslot((uint32_t)j, logcap);
             int2 *tab = (int2 *)t;
             for (uint32_t probe = 0; probe <= cmask; ++probe) {
                 int old = atomicCAS(&tab[h].x, -1, j);
@@ -103,20 +120,38 @@ struct PosTab {
         }
     }
 
+    // Packed: position of column j given the words w of its home bucket h, or
+    // -1 when j is not in the row. A slot holds j iff its word XOR (j << PB)
+    // is below 2^PB, and that value is then the position; at most one slot
+    // of a bucket holds j, so the minimum over the bucket decides.
+    __device__ __forceinline__ int find(int logcap, int j, uint32_t h, uint4 w) const
+    {
+        constexpr int PB = PackBits<CAP>::PB;
+        const uint32_t key = (uint32_t)j << PB, pm = (1u << PB) - 1u;
+        const uint32_t cmask = (1u << logcap) - 1u;
+        const uint32_t m = min(min(w.x ^ key, w.y ^ key), min(w.z ^ key, w.w ^ key));
+        if (m <= pm) return (int)m;
+        if (w.w == kEmpty) return -1;
+        // the home bucket is full: later buckets, rarely
+        for (uint32_t probe = 4; probe <= cmask; probe += 4) {
+            h = (h + 4u) & cmask;
+            const uint4 v = bucket(h);
+            const uint32_t mv = min(min(v.x ^ key, v.y ^ key), min(v.z ^ key, v.w ^ key));
+            if (mv <= pm) return (int)mv;
+            if (v.w == kEmpty) return -1;
+        }
+        return -1;
+    }
+
     // position of column j in the row, or -1 when j is not in the row
     __device__ __forceinline__ int lookup(int logcap, int j) const
     {
-        const uint32_t cmask = (1u << logcap) - 1u;
-        uint32_t h = hslot((uint32_t)j, logcap);
         if (PACK) {
-            constexpr int PB = PackBits<CAP>::PB;
-            for (uint32_t probe = 0; probe <= cmask; ++probe) {
-                const uint32_t v = t[h];
-                if ((v >> PB) == (uint32_t)j) return (int)(v & ((1u << PB) - 1u));
-                if (v == 0xffffffffu) return -1;
-                h = (h + 1u) & cmask;
-            }
+            const uint32_t h = home(logcap, j);
+            return find(logcap, j, h, bucket(h));
         } else {
+            const uint32_t cmask = (1u << logcap) - 1u;
+            uint32_t h = hslot((uint32_t)j, logcap);
             const int2 *tab = (const int2 *)t;
             for (uint32_t probe = 0; probe <= cmask; ++probe) {
                 const int2 v = tab[h];
@@ -126,6 +161,32 @@ struct PosTab {
             }
         }
         return -1;
+    }
+
+    // positions of D columns (-2 where jv < 0): the home buckets of all D are
+    // read before any is searched
+    template <int D>
+    __device__ __forceinline__ void lookup_n(int logcap, const int (&jv)[D], int (&pos)[D]) const
+    {
+        static_assert(D % 2 == 0, "looked up in pairs");
+        if (PACK) {
+            // two at a time: four buckets in registers would cost 16 VGPRs
+#pragma unroll
+            for (int d0 = 0; d0 < D; d0 += 2) {
+                uint32_t hv[2];
+                uint4 wv[2];
+#pragma unroll
+                for (int d = 0; d < 2; ++d) hv[d] = jv[d0 + d] >= 0 ? home(logcap, jv[d0 + d]) : 0u;
+#pragma unroll
+                for (int d = 0; d < 2; ++d) wv[d] = bucket(hv[d]);
+#pragma unroll
+                for (int d = 0; d < 2; ++d)
+                    pos[d0 + d] = jv[d0 + d] >= 0 ? find(logcap, jv[d0 + d], hv[d], wv[d]) : -2;
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < D; ++d) pos[d] = jv[d] >= 0 ? lookup(logcap, jv[d]) : -2;
+        }
     }
 };
 
@@ -255,6 +316,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
           : NumShape<G, CAP, PACK, FLAT>::OCC))) void k_num_lds(Batch b, Sched sc, int bin)
 {
     constexpr int kNumDepth = NumShape<G, CAP, PACK, FLAT>::DEPTH;
+    static_assert(FLAT || G % kNumDepth == 0, "the staged entries are read kNumDepth at a time");
     constexpr int W = kWave / G;
     constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
     constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
@@ -367,11 +429,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
                         }
                     }
                     int posv[kNumDepth];
+                    tab.template lookup_n<kNumDepth>(logcap, jv, posv);
 #pragma unroll
-                    for (int d = 0; d < kNumDepth; ++d) {
-                        posv[d] = jv[d] >= 0 ? tab.lookup(logcap, jv[d]) : -2;
+                    for (int d = 0; d < kNumDepth; ++d)
                         if (posv[d] == -1) bad = true;
-                    }
 #pragma unroll
                     for (int d = 0; d < kNumDepth; ++d) {
                         bool pend = posv[d] >= 0;
@@ -390,42 +451,51 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
                 }
             }
             for (int u0 = 0; u0 < n; u0 += kNumDepth) {
-                // issue the B loads of kNumDepth steps, then accumulate them in order
+                // issue the B loads of kNumDepth steps, then accumulate them in order.
+                // The staged entries are read together (all G are written every
+                // chunk, those past the row as empty ranges, and G is a multiple of
+                // kNumDepth).
+                int2 qr[kNumDepth];
+#pragma unroll
+                for (int d = 0; d < kNumDepth; ++d) qr[d] = *(const int2 *)(par + u0 + d);
+                bool longs = false;   // a step whose row of B is longer than G
+#pragma unroll
+                for (int d = 0; d < kNumDepth; ++d) longs |= qr[d].y - qr[d].x > G;
+                if (__ballot(longs)) {
+                    // one step at a time, each through all of its row of B: its
+                    // entries have distinct columns, so the order is kept
+#pragma unroll 1
+                    for (int d = 0; d < kNumDepth; ++d) {
+                        const int4 pr = par[u0 + d];
+                        const double a = __hiloint2double(pr.w, pr.z);
+                        for (int q = pr.x + lane; q < pr.y; q += G) {
+                            const int pos = tab.lookup(logcap, bci[q]);
+                            if (pos >= 0) atomicAdd(acc + pos, a * bval[q]);
+                            else bad = true;
+                        }
+                    }
+                    continue;
+                }
                 int jv[kNumDepth];
                 double bv[kNumDepth], av[kNumDepth];
-                uint32_t longm = 0;   // steps whose row of B is longer than G
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) {
-                    jv[d] = -1; bv[d] = 0.0; av[d] = 0.0;
-                    if (u0 + d < n) {
-                        const int4 pr = par[u0 + d];
-                        const int q0 = pr.x, q1 = pr.y;
-                        av[d] = __hiloint2double(pr.w, pr.z);
-                        if (q1 - q0 > G) longm |= 1u << d;
-                        const int q = q0 + lane;
-                        if (q < q1) { jv[d] = bci[q]; bv[d] = bval[q]; }
-                    }
+                    jv[d] = -1; bv[d] = 0.0;
+                    const int q = qr[d].x + lane;
+                    if (q < qr[d].y) { jv[d] = bci[q]; bv[d] = bval[q]; }
                 }
+#pragma unroll
+                for (int d = 0; d < kNumDepth; ++d) av[d] = *((const double *)(par + u0 + d) + 1);
                 // positions first (independent LDS reads), then the adds in step
                 // order; within a step the lanes hold distinct columns of B_k, so
                 // no two lanes add to the same slot and every slot gets its terms
                 // in ascending k. The LDS fp64 add rounds like a plain add.
                 int posv[kNumDepth];
-#pragma unroll
-                for (int d = 0; d < kNumDepth; ++d) posv[d] = jv[d] >= 0 ? tab.lookup(logcap, jv[d]) : -2;
+                tab.template lookup_n<kNumDepth>(logcap, jv, posv);
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) {
                     if (posv[d] >= 0) atomicAdd(acc + posv[d], av[d] * bv[d]);
                     else if (posv[d] == -1) bad = true;
-                    if ((longm >> d) & 1u) {
-                        const int4 pr = par[u0 + d];
-                        const int q0 = pr.x, q1 = pr.y;
-                        for (int q = q0 + G + lane; q < q1; q += G) {
-                            const int pos = tab.lookup(logcap, bci[q]);
-                            if (pos >= 0) atomicAdd(acc + pos, av[d] * bval[q]);
-                            else bad = true;
-                        }
-                    }
                 }
             }
             nwave_sync();
@@ -638,12 +708,13 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
                             tv[d] = __hiloint2double(pr.w, pr.z) * bval[q];
                         }
                     }
-                    int posv[kWinDepth];
+                    int jw[kWinDepth], posv[kWinDepth];
 #pragma unroll
-                    for (int d = 0; d < kWinDepth; ++d) {
-                        posv[d] = (jv[d] >= 0 && jv[d] >= jlo && jv[d] <= jhi) ? tab.lookup(logcap, jv[d]) : -2;
+                    for (int d = 0; d < kWinDepth; ++d) jw[d] = (jv[d] >= jlo && jv[d] <= jhi) ? jv[d] : -1;
+                    tab.template lookup_n<kWinDepth>(logcap, jw, posv);
+#pragma unroll
+                    for (int d = 0; d < kWinDepth; ++d)
                         if (posv[d] == -1) bad = true;
-                    }
 #pragma unroll
                     for (int d = 0; d < kWinDepth; ++d) {
                         bool pend = posv[d] >= 0;
