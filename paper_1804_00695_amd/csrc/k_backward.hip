@@ -40,17 +40,62 @@ constexpr int nw_bwd(int row_bytes, int rows_per_wave)
     return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
 }
 
-__device__ __forceinline__ bool w_lookup(const int *key, const double *wv, int logcap, int j, double &w)
+// W_i's hash: column keys (-1 empty) in buckets of 4 slots (16 bytes), W
+// values beside them. A column takes the first empty slot at or after the
+// start of its home bucket, so a bucket's filled slots are a prefix of it and
+// a bucket whose last slot is empty ends a search.
+__device__ __forceinline__ uint32_t w_home(int logcap, int j) { return hslot((uint32_t)j, logcap - 2) << 2; }
+
+__device__ __forceinline__ void w_insert(int *key, double *wv, int logcap, int j, double w)
 {
     const uint32_t cmask = (1u << logcap) - 1u;
-    uint32_t h = hslot((uint32_t)j, logcap);
-    for (uint32_t probe = 0; probe <= cmask; ++probe) {
-        int k = key[h];
-        if (k == j) { w = wv[h]; return true; }
-        if (k == -1) return false;
-        h = (h + 1u) & cmask;
+    uint32_t h = w_home(logcap, j);
+    for (uint32_t probe = 0; probe <= cmask; probe += 4) {
+        const int4 k = *(const int4 *)(key + h);
+        int sl = k.x == -1 ? 0 : (k.y == -1 ? 1 : (k.z == -1 ? 2 : (k.w == -1 ? 3 : 4)));
+        for (; sl < 4; ++sl)
+            if (atomicCAS(key + h + sl, -1, j) == -1) { wv[h + sl] = w; return; }
+        h = (h + 4u) & cmask;
     }
-    return false;
+}
+
+// slot of column j given the keys k of its home bucket h, or -1 when absent
+__device__ __forceinline__ int w_slot(const int *key, int logcap, int j, uint32_t h, int4 k)
+{
+    const int sl = k.x == j ? 0 : (k.y == j ? 1 : (k.z == j ? 2 : (k.w == j ? 3 : -1)));
+    if (sl >= 0) return (int)h + sl;
+    if (k.w == -1) return -1;
+    const uint32_t cmask = (1u << logcap) - 1u;
+    for (uint32_t probe = 4; probe <= cmask; probe += 4) {   // the home bucket is full: rarely
+        h = (h + 4u) & cmask;
+        const int4 v = *(const int4 *)(key + h);
+        const int s2 = v.x == j ? 0 : (v.y == j ? 1 : (v.z == j ? 2 : (v.w == j ? 3 : -1)));
+        if (s2 >= 0) return (int)h + s2;
+        if (v.w == -1) return -1;
+    }
+    return -1;
+}
+
+// slots of D columns (-2 where jv < 0), the home buckets of a pair read
+// before either is searched, then the W values of all D read together
+template <int D>
+__device__ __forceinline__ void w_lookup_n(const int *key, const double *wv, int logcap, const int (&jv)[D],
+                                           int (&sl)[D], double (&w)[D])
+{
+    static_assert(D % 2 == 0, "looked up in pairs");
+#pragma unroll
+    for (int d0 = 0; d0 < D; d0 += 2) {
+        uint32_t hv[2];
+        int4 kv[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) hv[d] = jv[d0 + d] >= 0 ? w_home(logcap, jv[d0 + d]) : 0u;
+#pragma unroll
+        for (int d = 0; d < 2; ++d) kv[d] = *(const int4 *)(key + hv[d]);
+#pragma unroll
+        for (int d = 0; d < 2; ++d) sl[d0 + d] = jv[d0 + d] >= 0 ? w_slot(key, logcap, jv[d0 + d], hv[d], kv[d]) : -2;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) w[d] = wv[sl[d] >= 0 ? sl[d] : 0];
 }
 
 // LDS of one row: W_i's hash (key, value), the staged entries of A (first B
@@ -103,7 +148,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
 {
     constexpr int W = kWave / G;
     constexpr int NW = nw_bwd_best(bwd_row_bytes(CAP, G) * W);
-    __shared__ int s_key[NW * W * CAP];
+    __shared__ __attribute__((aligned(16))) int s_key[NW * W * CAP];
     __shared__ double s_wv[NW * W * CAP];
     __shared__ double s_pa[NW * W * G];
     __shared__ double s_da[NW * W * G];
@@ -148,7 +193,6 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
         int logcap = ilog2_ceil(2 * nw);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
-        const uint32_t cmask = (uint32_t)cap - 1u;
         for (int h = lane; h < cap; h += G) key[h] = -1;
         // the first chunk of A_i is in flight while W_i is hashed
         int ka = -1;
@@ -167,14 +211,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
                     if (e < nw) { jv[u] = wci[ws0 + e]; wj[u] = wval[ws0 + e]; }
                 }
 #pragma unroll
-                for (int u = 0; u < kBwdInsDepth; ++u) {
-                    if (jv[u] < 0) continue;
-                    uint32_t h = hslot((uint32_t)jv[u], logcap);
-                    for (uint32_t probe = 0; probe <= cmask; ++probe) {
-                        if (atomicCAS(key + h, -1, jv[u]) == -1) { wv[h] = wj[u]; break; }
-                        h = (h + 1u) & cmask;
-                    }
-                }
+                for (int u = 0; u < kBwdInsDepth; ++u)
+                    if (jv[u] >= 0) w_insert(key, wv, logcap, jv[u], wj[u]);
             }
         }
         m = bwd_meta(P, sc, g_n);   // the next row's metadata, in flight during this row
@@ -229,13 +267,15 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
                         bv[d] = bval[qv[d]];
                     }
                 }
+                int sl[kBwdUnroll];
+                double w[kBwdUnroll];
+                w_lookup_n<kBwdUnroll>(key, wv, logcap, jv, sl, w);
 #pragma unroll
                 for (int d = 0; d < kBwdUnroll; ++d) {
-                    if (jv[d] < 0) continue;
-                    double w;
-                    if (!w_lookup(key, wv, logcap, jv[d], w)) { bad = true; continue; }
-                    if (dA) atomicAdd(da + ev[d], w * bv[d]);
-                    if (dB) atomicAdd(dB + qv[d], pa[ev[d]] * w);
+                    if (sl[d] == -1) bad = true;
+                    if (sl[d] < 0) continue;
+                    if (dA) atomicAdd(da + ev[d], w[d] * bv[d]);
+                    if (dB) atomicAdd(dB + qv[d], pa[ev[d]] * w[d]);
                 }
             }
             bwd_sync();
@@ -286,7 +326,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
     constexpr int G = kWave;
     constexpr int M = CAP / 2;
     constexpr int NW = nw_bwd(bwd_win_bytes(CAP), 1);
-    __shared__ int s_key[NW * CAP];
+    __shared__ __attribute__((aligned(16))) int s_key[NW * CAP];
     __shared__ double s_wv[NW * CAP];
     __shared__ int4 s_par[NW * G];        // staged entries: (first B position, -, a)
     __shared__ int s_poff[NW * (G + 1)];  // first pair of each staged entry, then the total
@@ -349,7 +389,6 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
             int logcap = ilog2_ceil(2 * n);
             if (logcap < 5) logcap = 5;
             const int cap = 1 << logcap;
-            const uint32_t cmask = (uint32_t)cap - 1u;
             for (int h = lane; h < cap; h += G) key[h] = -1;
             bwd_sync();
             for (int e0 = lane; e0 < n; e0 += G * kBwdInsDepth) {
@@ -363,14 +402,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
                     if (e < n) { jv[u] = wci[ws0 + e]; wj[u] = wval[ws0 + e]; }
                 }
 #pragma unroll
-                for (int u = 0; u < kBwdInsDepth; ++u) {
-                    if (jv[u] < 0) continue;
-                    uint32_t h = hslot((uint32_t)jv[u], logcap);
-                    for (uint32_t probe = 0; probe <= cmask; ++probe) {
-                        if (atomicCAS(key + h, -1, jv[u]) == -1) { wv[h] = wj[u]; break; }
-                        h = (h + 1u) & cmask;
-                    }
-                }
+                for (int u = 0; u < kBwdInsDepth; ++u)
+                    if (jv[u] >= 0) w_insert(key, wv, logcap, jv[u], wj[u]);
             }
             bwd_sync();
             bool bad = false;
@@ -422,14 +455,17 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
                             bv[d] = bval[qv[d]];
                         }
                     }
+                    int jw[kBwdWinDepth], sl[kBwdWinDepth];
+                    double w[kBwdWinDepth];
+#pragma unroll
+                    for (int d = 0; d < kBwdWinDepth; ++d) jw[d] = (jv[d] >= jlo && jv[d] <= jhi) ? jv[d] : -1;
+                    w_lookup_n<kBwdWinDepth>(key, wv, logcap, jw, sl, w);
 #pragma unroll
                     for (int d = 0; d < kBwdWinDepth; ++d) {
-                        const int j = jv[d];
-                        if (j < 0 || j < jlo || j > jhi) continue;
-                        double w;
-                        if (!w_lookup(key, wv, logcap, j, w)) { bad = true; continue; }
-                        if (dA) atomicAdd(da + ev[d], w * bv[d]);
-                        if (dB) atomicAdd(dB + qv[d], av[d] * w);
+                        if (sl[d] == -1) bad = true;
+                        if (sl[d] < 0) continue;
+                        if (dA) atomicAdd(da + ev[d], w[d] * bv[d]);
+                        if (dB) atomicAdd(dB + qv[d], av[d] * w[d]);
                     }
                 }
                 bwd_sync();

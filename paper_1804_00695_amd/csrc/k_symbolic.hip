@@ -23,6 +23,9 @@ namespace mls {
 
 constexpr uint32_t kEmptyKey = 0xffffffffu;
 constexpr int kSymBatch = 6;   // words of one B_k row loaded before they are inserted (measured)
+// fewer where 32 or more lanes own a row (their count kernels run at 6 waves per SIMD)
+template <int G, bool FILL>
+constexpr int sym_batch() { return (!FILL && G >= 32) ? 4 : kSymBatch; }
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -38,19 +41,18 @@ constexpr int nw_for(int row_bytes, int rows_per_wave)
     return nw > 4 ? 4 : (nw < 1 ? 1 : nw);
 }
 
-__device__ __forceinline__ void set_insert(uint32_t *key, uint32_t *msk, int logcap, uint32_t s, uint32_t m,
-                                           uint32_t *err)
+// OR mask m into the slot of set s, given the word k read from its home slot
+// h (possibly before other lanes' inserts: an empty slot is claimed with a
+// compare-and-swap, whose result is the slot's current key)
+__device__ __forceinline__ void set_insert_at(uint32_t *key, uint32_t *msk, int logcap, uint32_t s, uint32_t m,
+                                              uint32_t h, uint32_t k, uint32_t *err)
 {
     const uint32_t cmask = (1u << logcap) - 1u;
-    uint32_t h = hslot(s, logcap);
     for (uint32_t probe = 0; probe <= cmask; ++probe) {
-        uint32_t k = __hip_atomic_load(key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == s) { atomicOr(msk + h, m); return; }
-        if (k == kEmptyKey) {
-            uint32_t old = atomicCAS(key + h, kEmptyKey, s);
-            if (old == kEmptyKey || old == s) { atomicOr(msk + h, m); return; }
-        }
+        if (k == kEmptyKey) k = atomicCAS(key + h, kEmptyKey, s);
+        if (k == kEmptyKey || k == s) { atomicOr(msk + h, m); return; }
         h = (h + 1u) & cmask;
+        k = __hip_atomic_load(key + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     atomicOr(err, kErrTable);
 }
@@ -81,6 +83,7 @@ template <int G, int CAP, bool FILL>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 6))) void k_sym_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
+    constexpr int SB = sym_batch<G, FILL>();
     constexpr int ROWB = FILL ? CAP * 12 : CAP * 8;
     constexpr int NW = nw_for(ROWB, W);
     constexpr int LIST = FILL ? CAP / 2 : 1;
@@ -160,14 +163,22 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 
                     nw = bwc[kl];
                 }
                 const MLS_G u32x2 *w = bw + q0;
-                for (int x = 0; x < nw; x += kSymBatch) {
-                    u32x2 wd[kSymBatch];
+                for (int x = 0; x < nw; x += SB) {
+                    u32x2 wd[SB];
 #pragma unroll
-                    for (int d = 0; d < kSymBatch; ++d)
+                    for (int d = 0; d < SB; ++d)
                         if (x + d < nw) wd[d] = w[x + d];
+                    // the home slots of all the words are read before any is
+                    // updated, so their LDS latencies overlap
+                    uint32_t hv[SB], kv[SB];
 #pragma unroll
-                    for (int d = 0; d < kSymBatch; ++d)
-                        if (x + d < nw) set_insert(key, msk, logcap, wd[d].x, wd[d].y, sc.err);
+                    for (int d = 0; d < SB; ++d) hv[d] = x + d < nw ? hslot(wd[d].x, logcap) : 0u;
+#pragma unroll
+                    for (int d = 0; d < SB; ++d)
+                        kv[d] = __hip_atomic_load(key + hv[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+                    for (int d = 0; d < SB; ++d)
+                        if (x + d < nw) set_insert_at(key, msk, logcap, wd[d].x, wd[d].y, hv[d], kv[d], sc.err);
                 }
             }
         }
