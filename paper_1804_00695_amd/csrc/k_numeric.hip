@@ -35,7 +35,10 @@ constexpr int kNumDepth = 4;   // steps whose B loads are issued together (8 whe
 constexpr int kNumWinCap = 1024;   // table slots of a spill window (CAP / 2 positions)
 constexpr int kWinDepth = 2;
 constexpr bool kNumFlat = true;    // flattened pairs for the classes of at most kNumFlatMaxG lanes per row
-constexpr int kNumFlatMaxG = 8;       // spill window: batches of 64 pairs whose B loads are issued together
+constexpr int kNumFlatMaxG = 8;
+
+// all ones: read as a column it is -1 (no entry)
+__device__ __attribute__((aligned(8))) int32_t k_num_void[2] = {-1, -1};       // spill window: batches of 64 pairs whose B loads are issued together
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -124,15 +127,21 @@ struct PosTab {
     // -1 when j is not in the row. A slot holds j iff its word XOR (j << PB)
     // is below 2^PB, and that value is then the position; at most one slot
     // of a bucket holds j, so the minimum over the bucket decides.
-    __device__ __forceinline__ int find(int logcap, int j, uint32_t h, uint4 w) const
+    __device__ __forceinline__ int find(int logcap, int j, uint32_t h, uint4 w, bool live = true) const
     {
         constexpr int PB = PackBits<CAP>::PB;
         const uint32_t key = (uint32_t)j << PB, pm = (1u << PB) - 1u;
-        const uint32_t cmask = (1u << logcap) - 1u;
         const uint32_t m = min(min(w.x ^ key, w.y ^ key), min(w.z ^ key, w.w ^ key));
-        if (m <= pm) return (int)m;
-        if (w.w == kEmpty) return -1;
-        // the home bucket is full: later buckets, rarely
+        int p = m <= pm ? (int)m : -1;
+        if (live && m > pm && w.w != kEmpty) p = find_more(logcap, key, h);
+        return p;
+    }
+
+    // the search past a full home bucket h (rarely needed)
+    __device__ __forceinline__ int find_more(int logcap, uint32_t key, uint32_t h) const
+    {
+        constexpr int PB = PackBits<CAP>::PB;
+        const uint32_t pm = (1u << PB) - 1u, cmask = (1u << logcap) - 1u;
         for (uint32_t probe = 4; probe <= cmask; probe += 4) {
             h = (h + 4u) & cmask;
             const uint4 v = bucket(h);
@@ -180,8 +189,11 @@ struct PosTab {
 #pragma unroll
                 for (int d = 0; d < 2; ++d) wv[d] = bucket(hv[d]);
 #pragma unroll
-                for (int d = 0; d < 2; ++d)
-                    pos[d0 + d] = jv[d0 + d] >= 0 ? find(logcap, jv[d0 + d], hv[d], wv[d]) : -2;
+                for (int d = 0; d < 2; ++d) {
+                    const bool live = jv[d0 + d] >= 0;
+                    const int p = find(logcap, jv[d0 + d], hv[d], wv[d], live);
+                    pos[d0 + d] = live ? p : -2;
+                }
             }
         } else {
 #pragma unroll
@@ -478,12 +490,20 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
                 }
                 int jv[kNumDepth];
                 double bv[kNumDepth], av[kNumDepth];
+                // lanes past their row of B load the all-ones dummy instead
+                // (column -1: no lookup, no add), so no branch surrounds the loads
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) {
-                    jv[d] = -1; bv[d] = 0.0;
                     const int q = qr[d].x + lane;
-                    if (q < qr[d].y) { jv[d] = bci[q]; bv[d] = bval[q]; }
+                    const bool ok = q < qr[d].y;
+                    const MLS_G int32_t *pj = ok ? bci + q : (const MLS_G int32_t *)k_num_void;
+                    const MLS_G double *pv = ok ? bval + q : (const MLS_G double *)k_num_void;
+                    jv[d] = *pj;
+                    bv[d] = *pv;
                 }
+                // keep the scheduler from hoisting uses of the loaded columns
+                // above the later loads (each would wait for a load)
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) av[d] = *((const double *)(par + u0 + d) + 1);
                 // positions first (independent LDS reads), then the adds in step
@@ -492,6 +512,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
                 // in ascending k. The LDS fp64 add rounds like a plain add.
                 int posv[kNumDepth];
                 tab.template lookup_n<kNumDepth>(logcap, jv, posv);
+                // every loaded value is consumed on every path (an empty asm
+                // use), so no load is left pending into the next batch
+#pragma unroll
+                for (int d = 0; d < kNumDepth; ++d) asm volatile("" ::"v"(bv[d]));
 #pragma unroll
                 for (int d = 0; d < kNumDepth; ++d) {
                     if (posv[d] >= 0) atomicAdd(acc + posv[d], av[d] * bv[d]);
