@@ -79,8 +79,22 @@ __device__ __forceinline__ SymRow sym_row(const Batch &b, const Sched &sc, int g
     return m;
 }
 
+// Waves per SIMD that the count kernel's LDS leaves resident (160 KB per CU,
+// 4 SIMDs), at most 6 (registers for the batched inserts); the kernel is
+// compiled to fit that many.
+template <int G, int CAP>
+constexpr int sym_count_waves()
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_for(CAP * 8, W);
+    constexpr int wgs = 163840 / (NW * W * CAP * 8);
+    constexpr int w = wgs * NW / 4;
+    return w > 6 ? 6 : (w < 1 ? 1 : w);
+}
+
 template <int G, int CAP, bool FILL>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 6))) void k_sym_lds(Batch b, Sched sc, int bin)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : sym_count_waves<G, CAP>())))
+void k_sym_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
     constexpr int SB = sym_batch<G, FILL>();
@@ -176,9 +190,19 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : 
 #pragma unroll
                     for (int d = 0; d < SB; ++d)
                         kv[d] = __hip_atomic_load(key + hv[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    // empty home slots claimed together, then the ORs; a word
+                    // whose home slot holds another set probes on
 #pragma unroll
                     for (int d = 0; d < SB; ++d)
-                        if (x + d < nw) set_insert_at(key, msk, logcap, wd[d].x, wd[d].y, hv[d], kv[d], sc.err);
+                        if (x + d < nw && kv[d] == kEmptyKey) kv[d] = atomicCAS(key + hv[d], kEmptyKey, wd[d].x);
+#pragma unroll
+                    for (int d = 0; d < SB; ++d) {
+                        if (x + d >= nw) continue;
+                        if (kv[d] == kEmptyKey || kv[d] == wd[d].x)
+                            atomicOr(msk + hv[d], wd[d].y);
+                        else
+                            set_insert_at(key, msk, logcap, wd[d].x, wd[d].y, hv[d], kv[d], sc.err);
+                    }
                 }
             }
         }
