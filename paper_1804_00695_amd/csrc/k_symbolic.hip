@@ -624,8 +624,12 @@ template <int G, int NLO>
 __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
 {
     static_assert(G <= kExpandMid && NLO < G, "row sizes (NLO, G] of at most kExpandMid words");
+    // the group's keys, exchanged through LDS (four per read) rather than by
+    // one cross-lane shuffle per key
+    __shared__ __attribute__((aligned(16))) uint32_t s_k[kWG];
     const int lane64 = threadIdx.x & 63;
     const int slot = lane64 / G, lane = lane64 % G;
+    uint32_t *gk = s_k + (threadIdx.x & ~63) + slot * G;
     const int nw = (int)gridDim.x * (kWG / kWave);
     const int w0 = (int)((blockIdx.x * kWG + threadIdx.x) >> 6);
     const MLS_G int32_t *scnt = gp(sc.scnt);
@@ -654,12 +658,16 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
             if (lane < n) w = scr[(int64_t)g * kScratchWords + lane];
             const uint32_t kb = w.x << 6;
             const uint32_t key = kb | (uint32_t)(lane < n ? __popc(w.y) : 0);
+            gk[lane] = key;
+            wave_sync();
             int off = 0;
 #pragma unroll
-            for (int f = 0; f < G; ++f) {
-                const uint32_t kf = (uint32_t)__shfl((int)key, f, G);
-                off += kf < kb ? (int)(kf & 63u) : 0;
+            for (int f = 0; f < G; f += 4) {
+                const uint4 q = *(const uint4 *)(gk + f);
+                off += (q.x < kb ? (int)(q.x & 63u) : 0) + (q.y < kb ? (int)(q.y & 63u) : 0) +
+                       (q.z < kb ? (int)(q.z & 63u) : 0) + (q.w < kb ? (int)(q.w & 63u) : 0);
             }
+            wave_sync();
             if (lane < n) {
                 const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
                 const Prob P = get_prob(b, t);
