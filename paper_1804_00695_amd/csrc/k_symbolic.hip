@@ -528,6 +528,7 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
 static_assert(kScratchWords == kWave, "one scratch word per lane");
 constexpr int kExpandSmall = 16;   // rows with at most this many words take the 16-lane kernel
 constexpr int kExpandMid = 32;     // rows with at most this many words take the 32-lane kernel
+constexpr int kExpandStage = 256;  // columns of a row staged in LDS before the ordered write-out
 
 struct ExpandRow {
     int cs, ce, t;
@@ -627,9 +628,14 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
     // the group's keys, exchanged through LDS (four per read) rather than by
     // one cross-lane shuffle per key
     __shared__ __attribute__((aligned(16))) uint32_t s_k[kWG];
+    // a row's columns are placed in LDS first and written out in order, so
+    // that the stores of a group are contiguous (rows of at most
+    // kExpandStage columns; longer ones are written lane by lane)
+    __shared__ int32_t s_col[(kWG / G) * kExpandStage];
     const int lane64 = threadIdx.x & 63;
     const int slot = lane64 / G, lane = lane64 % G;
     uint32_t *gk = s_k + (threadIdx.x & ~63) + slot * G;
+    int32_t *gc = s_col + (threadIdx.x / G) * kExpandStage;
     const int nw = (int)gridDim.x * (kWG / kWave);
     const int w0 = (int)((blockIdx.x * kWG + threadIdx.x) >> 6);
     const MLS_G int32_t *scnt = gp(sc.scnt);
@@ -660,31 +666,44 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
             const uint32_t key = kb | (uint32_t)(lane < n ? __popc(w.y) : 0);
             gk[lane] = key;
             wave_sync();
-            int off = 0;
+            int off = 0, tot = 0;
 #pragma unroll
             for (int f = 0; f < G; f += 4) {
                 const uint4 q = *(const uint4 *)(gk + f);
                 off += (q.x < kb ? (int)(q.x & 63u) : 0) + (q.y < kb ? (int)(q.y & 63u) : 0) +
                        (q.z < kb ? (int)(q.z & 63u) : 0) + (q.w < kb ? (int)(q.w & 63u) : 0);
+                tot += (int)((q.x & 63u) + (q.y & 63u) + (q.z & 63u) + (q.w & 63u));
             }
             wave_sync();
-            if (lane < n) {
+            if (n > 0) {
                 const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
                 const Prob P = get_prob(b, t);
                 const int i = g - (b.nprob == 1 ? 0 : pc.lo);
                 const int cs = gp(P.crp)[i] - P.c_off;
                 const int ce = gp(P.crp)[i + 1] - P.c_off;
                 MLS_G int32_t *__restrict__ cci = gpw(P.cci);
-                uint32_t m = w.y;
-                int pos = cs + off;
-                while (m) {
-                    const int bit = __ffs(m) - 1;
-                    if (pos < ce) cci[pos] = (int32_t)(w.x * 32u + (uint32_t)bit);
-                    else atomicOr(sc.err, kErrStructure);
-                    ++pos;
-                    m &= m - 1u;
+                if (tot <= kExpandStage && tot <= ce - cs) {
+                    uint32_t m = lane < n ? w.y : 0u;
+                    int pos = off;
+                    while (m) {
+                        gc[pos++] = (int32_t)(w.x * 32u + (uint32_t)(__ffs(m) - 1));
+                        m &= m - 1u;
+                    }
+                    wave_sync();
+                    for (int e = lane; e < tot; e += G) cci[cs + e] = gc[e];
+                } else if (lane < n) {
+                    uint32_t m = w.y;
+                    int pos = cs + off;
+                    while (m) {
+                        const int bit = __ffs(m) - 1;
+                        if (pos < ce) cci[pos] = (int32_t)(w.x * 32u + (uint32_t)bit);
+                        else atomicOr(sc.err, kErrStructure);
+                        ++pos;
+                        m &= m - 1u;
+                    }
                 }
             }
+            wave_sync();
         }
     }
 }
