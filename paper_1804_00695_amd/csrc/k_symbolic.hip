@@ -620,7 +620,8 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
 
 // Rows of (NLO, G] words, G at most kExpandMid: a wave reads the word counts
 // of 64 consecutive rows and takes those rows 64 / G at a time, G lanes per
-// row; word f of a row is read from lane f of its group by a lane shuffle.
+// row; the group's (set, popcount) keys go through LDS, where every lane
+// reads all of them to rank its own word.
 template <int G, int NLO>
 __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
 {
