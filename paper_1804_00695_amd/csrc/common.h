@@ -173,13 +173,61 @@ __device__ __forceinline__ int ilog2_ceil(int x)
     return x <= 1 ? 0 : 32 - __clz(x - 1);
 }
 
-// Sum over the G consecutive lanes of a group (G a power of two <= 64).
+// Cross-lane sums and scans over the G consecutive lanes of a group (G a
+// power of two <= 64, groups aligned to G). Groups of at most 16 lanes lie in
+// one 16-lane DPP row, where DPP moves read a neighbour's register directly
+// (no LDS round trip): quad permutations and (half-)row mirrors for sums,
+// row shifts for scans; every read stays inside the group (or is masked
+// off). Wider groups use shuffles. All lanes of a group must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v)
 {
+    if constexpr (G <= 16 && sizeof(T) == 4 && T(-1) < T(0)) {
+        if constexpr (G >= 2) v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+        if constexpr (G >= 4) v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+        if constexpr (G >= 8) v += dpp_move<0x141>(v);   // row_half_mirror: the other quad of 8
+        if constexpr (G >= 16) v += dpp_move<0x140>(v);  // row_mirror: the other half of 16
+        return v;
+    } else {
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
-    return v;
+        for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+        return v;
+    }
+}
+
+// the group's total, given a lane's value v and its inclusive prefix incl
+template <int G>
+__device__ __forceinline__ int group_total(int v, int incl)
+{
+    if constexpr (G <= 16) return group_sum<G>(v);
+    else return __shfl(incl, G - 1, G);
+}
+
+// inclusive prefix sum over the group; lane = position in the group
+template <int G>
+__device__ __forceinline__ int group_scan_incl(int v, int lane)
+{
+    if constexpr (G <= 16) {
+        int y;
+        if constexpr (G >= 2) { y = dpp_move<0x111>(v); if (lane >= 1) v += y; }   // row_shr:1
+        if constexpr (G >= 4) { y = dpp_move<0x112>(v); if (lane >= 2) v += y; }   // row_shr:2
+        if constexpr (G >= 8) { y = dpp_move<0x114>(v); if (lane >= 4) v += y; }   // row_shr:4
+        if constexpr (G >= 16) { y = dpp_move<0x118>(v); if (lane >= 8) v += y; }  // row_shr:8
+        return v;
+    } else {
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            const int y = __shfl_up(v, o, G);
+            if (lane >= o) v += y;
+        }
+        return v;
+    }
 }
 
 // Row at position pos of perm, or -1 (and an error bit) when the position or

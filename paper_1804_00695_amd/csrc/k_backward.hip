@@ -235,13 +235,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
             ka = -1;
             sa = 0.0;
             if (pc + G + lane < pe) { ka = aci[pc + G + lane]; sa = aval[pc + G + lane]; }
-            int incl = np;
-#pragma unroll
-            for (int o = 1; o < G; o <<= 1) {
-                const int y = __shfl_up(incl, o, G);
-                if (lane >= o) incl += y;
-            }
-            const int total = __shfl(incl, G - 1, G);
+            int incl = group_scan_incl<G>(np, lane);
+            const int total = group_total<G>(np, incl);
             poff[lane] = incl - np;
             if (lane == 0) poff[G] = total;
             pq[lane] = q0;
@@ -422,13 +417,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_win(Batch b, Sched sc, double *dA, 
                     }
                 }
                 const int np = sq1 > sq0 ? sq1 - sq0 : 0;
-                int incl = np;
-#pragma unroll
-                for (int o = 1; o < G; o <<= 1) {
-                    const int y = __shfl_up(incl, o, G);
-                    if (lane >= o) incl += y;
-                }
-                const int total = __shfl(incl, G - 1, G);
+                int incl = group_scan_incl<G>(np, lane);
+                const int total = group_total<G>(np, incl);
                 poff[lane] = incl - np;
                 if (lane == 0) poff[G] = total;
                 par[lane] = make_int4(sq0, 0, __double2loint(sa), __double2hiint(sa));

@@ -404,13 +404,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
             int total = 0;
             if constexpr (FLAT) {
                 const int np = sq1 > sq0 ? sq1 - sq0 : 0;
-                int incl = np;
-#pragma unroll
-                for (int o = 1; o < G; o <<= 1) {
-                    const int y = __shfl_up(incl, o, G);
-                    if (lane >= o) incl += y;
-                }
-                total = __shfl(incl, G - 1, G);
+                int incl = group_scan_incl<G>(np, lane);
+                total = group_total<G>(np, incl);
                 poff[lane] = incl - np;
             }
             nwave_sync();
@@ -699,13 +694,8 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
                     }
                 }
                 const int np = sq1 > sq0 ? sq1 - sq0 : 0;
-                int incl = np;
-#pragma unroll
-                for (int o = 1; o < G; o <<= 1) {
-                    const int y = __shfl_up(incl, o, G);
-                    if (lane >= o) incl += y;
-                }
-                const int total = __shfl(incl, G - 1, G);
+                int incl = group_scan_incl<G>(np, lane);
+                const int total = group_total<G>(np, incl);
                 poff[lane] = incl - np;
                 if (lane == 0) poff[G] = total;
                 par[lane] = make_int4(sq0, 0, __double2loint(sa), __double2hiint(sa));

@@ -262,13 +262,8 @@ void k_sym_lds(Batch b, Sched sc, int bin)
                             for (int x = 0; x < per; ++x) nl += kk[x] != kEmptyKey;
                         }
                         // exclusive prefix of nl over the group
-                        int incl = nl;
-#pragma unroll
-                        for (int o = 1; o < G; o <<= 1) {
-                            const int y = __shfl_up(incl, o, G);
-                            if (lane >= o) incl += y;
-                        }
-                        const int tot = __shfl(incl, G - 1, G);
+                        int incl = group_scan_incl<G>(nl, lane);
+                        const int tot = group_total<G>(nl, incl);
                         if (active && nl) {
                             int w = base + incl - nl;
                             for (int x = 0; x < per; ++x)
@@ -323,12 +318,7 @@ void k_sym_lds(Batch b, Sched sc, int bin)
             const int e0 = min(lane * per, n), e1 = min(e0 + per, n);
             int run = 0;
             for (int e = e0; e < e1; ++e) run += __popc(list[e].y);
-            int incl = run;
-#pragma unroll
-            for (int o = 1; o < G; o <<= 1) {
-                const int y = __shfl_up(incl, o, G);
-                if (lane >= o) incl += y;
-            }
+            int incl = group_scan_incl<G>(run, lane);
             if (active) {
                 const int cs = gp(P.crp)[i] - P.c_off;
                 const int ce = gp(P.crp)[i + 1] - P.c_off;

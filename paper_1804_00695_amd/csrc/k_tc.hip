@@ -171,13 +171,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE))) void
                 nk = bwc[k];
             }
             const int np = (nk + PW - 1) / PW;
-            int incl = np;
-#pragma unroll
-            for (int o = 1; o < G; o <<= 1) {
-                const int y = __shfl_up(incl, o, G);
-                if (lane >= o) incl += y;
-            }
-            const int npieces = __shfl(incl, G - 1, G);
+            int incl = group_scan_incl<G>(np, lane);
+            const int npieces = group_total<G>(np, incl);
             poff[lane] = incl - np;
             pst[lane] = st;
             pnk[lane] = nk;
