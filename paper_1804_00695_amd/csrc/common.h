@@ -209,6 +209,26 @@ __device__ __forceinline__ int group_total(int v, int incl)
     else return __shfl(incl, G - 1, G);
 }
 
+// number of lower lanes of the group (G <= 16) whose key equals this lane's
+template <int O, int G>
+__device__ __forceinline__ void group_rank_step(int key, int lane, int &r)
+{
+    if constexpr (O < G) {
+        const int y = dpp_move<0x110 + O>(key);   // row_shr:O
+        r += (lane >= O && y == key) ? 1 : 0;
+        group_rank_step<O + 1, G>(key, lane, r);
+    }
+}
+
+template <int G>
+__device__ __forceinline__ int group_rank(int key, int lane)
+{
+    static_assert(G <= 16, "one DPP row");
+    int r = 0;
+    group_rank_step<1, G>(key, lane, r);
+    return r;
+}
+
 // inclusive prefix sum over the group; lane = position in the group
 template <int G>
 __device__ __forceinline__ int group_scan_incl(int v, int lane)

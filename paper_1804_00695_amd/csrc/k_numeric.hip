@@ -297,10 +297,10 @@ __device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, boo
 
 // FLAT: the (entry, B position) pairs of a staged chunk are flattened, G at a
 // time, one per lane (for rows of B shorter than G, which would leave lanes
-// idle); the adds of a step go in rounds in which the lowest pending lane of
-// every output position adds, so the terms still arrive in ascending k. Its
-// lane marks and the staged pair offsets follow the tables in LDS.
-constexpr int num_flat_words(int CAP, int G) { return CAP / 2 + G + 1; }
+// idle); the adds of a step go in rounds by the number of lower lanes with
+// the same output position, so the terms still arrive in ascending k. The
+// staged pair offsets follow the tables in LDS.
+constexpr int num_flat_words(int G) { return G + 1; }
 
 // Waves per SIMD that the LDS of one workgroup (NW waves) leaves resident:
 // 160 KB per CU, 4 SIMDs, at most 8 waves each.
@@ -314,7 +314,7 @@ constexpr int lds_waves_per_simd(int wg_bytes, int nw)
 template <int G, int CAP, bool PACK, bool FLAT>
 struct NumShape {
     static constexpr int W = kWave / G;
-    static constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
+    static constexpr int XW = FLAT ? num_flat_words(G) : 0;
     static constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
     static constexpr int OCC = lds_waves_per_simd(NW * W * (num_row_bytes(CAP, G, PACK) + 4 * XW), NW);
     // where LDS already limits a SIMD to 4 waves, registers are free for
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
     constexpr int kNumDepth = NumShape<G, CAP, PACK, FLAT>::DEPTH;
     static_assert(FLAT || G % kNumDepth == 0, "the staged entries are read kNumDepth at a time");
     constexpr int W = kWave / G;
-    constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
+    constexpr int XW = FLAT ? num_flat_words(G) : 0;
     constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
     constexpr int TW = PACK ? CAP : 2 * CAP;   // table words per row
     __shared__ __attribute__((aligned(16))) uint32_t s_tab[NW * W * (TW + XW)];
@@ -345,8 +345,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
     PosTab<CAP, PACK> tab{s_tab + rs * TW};
     double *acc = s_acc + rs * (CAP / 2);
     int4 *par = s_par + rs * G;
-    int *own = (int *)(s_tab + NW * W * TW) + rs * XW;   // FLAT only: lane marks, then pair offsets
-    int *poff = own + CAP / 2;
+    int *poff = (int *)(s_tab + NW * W * TW) + rs * XW;   // FLAT only: staged pair offsets
 
     const int n_bin = gp(sc.bin_count)[bin];
     const int start = bin_start(sc.bin_count, bin);
@@ -440,19 +439,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
                     for (int d = 0; d < kNumDepth; ++d)
                         if (posv[d] == -1) bad = true;
+                    // lanes of a step holding the same output add in lane (= term)
+                    // order: a lane's round is the number of lower lanes of its
+                    // group with the same position, and one wave's LDS adds take
+                    // effect in program order
 #pragma unroll
                     for (int d = 0; d < kNumDepth; ++d) {
-                        bool pend = posv[d] >= 0;
-                        while (__ballot(pend)) {
-                            if (pend) own[posv[d]] = G;
-                            nwave_sync();
-                            if (pend) atomicMin(own + posv[d], lane);
-                            nwave_sync();
-                            if (pend && own[posv[d]] == lane) {
-                                atomicAdd(acc + posv[d], tv[d]);
-                                pend = false;
-                            }
-                            nwave_sync();
+                        const int rk = posv[d] >= 0 ? group_rank<G>(posv[d], lane) : -1;
+                        for (int rr = 0;; ++rr) {
+                            if (rk == rr) atomicAdd(acc + posv[d], tv[d]);
+                            if (!__ballot(rk > rr)) break;
                         }
                     }
                 }
@@ -770,7 +766,7 @@ template <int G, int CAP, bool PACK, bool MULTI, bool FLAT>
 static void launch_num_variant(const Batch &b, const Sched &sc, int bin, hipStream_t s)
 {
     constexpr int W = kWave / G;
-    constexpr int XW = FLAT ? num_flat_words(CAP, G) : 0;
+    constexpr int XW = FLAT ? num_flat_words(G) : 0;
     constexpr int NW = nw_num(num_row_bytes(CAP, G, PACK) + 4 * XW, W);
     static int grid = persistent_grid_n(k_num_lds<G, CAP, PACK, MULTI, FLAT>, NW * kWave);
     static char name[64];
