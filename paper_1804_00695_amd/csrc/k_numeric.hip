@@ -300,7 +300,7 @@ __device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, boo
 // idle); the adds of a step go in rounds by the number of lower lanes with
 // the same output position, so the terms still arrive in ascending k. The
 // staged pair offsets follow the tables in LDS.
-constexpr int num_flat_words(int G) { return G + 1; }
+constexpr int num_flat_words(int G) { return G; }
 
 // Waves per SIMD that the LDS of one workgroup (NW waves) leaves resident:
 // 160 KB per CU, 4 SIMDs, at most 8 waves each.
@@ -414,28 +414,44 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
             if (pc + G + lane < pe) { ka = aci[pc + G + lane]; sa = aval[pc + G + lane]; }
             const int n = FLAT ? 0 : min(G, pe - pc);
             if constexpr (FLAT) {
+                // the group's pair offsets in registers: a pair's entry is the
+                // last one whose offset is at most the pair's index
+                static_assert(G % 4 == 0 && G <= 16, "offsets read four at a time");
+                int pofv[G];
+#pragma unroll
+                for (int x = 0; x < G; x += 4) {
+                    const int4 v = *(const int4 *)(poff + x);
+                    pofv[x] = v.x; pofv[x + 1] = v.y; pofv[x + 2] = v.z; pofv[x + 3] = v.w;
+                }
                 for (int base = 0; base < total; base += G * kNumDepth) {
                     int jv[kNumDepth];
-                    double tv[kNumDepth];
+                    double av[kNumDepth], bv[kNumDepth];
+                    // loads without branches (pairs past the chunk read the
+                    // all-ones dummy: column -1), all issued before any use
 #pragma unroll
                     for (int d = 0; d < kNumDepth; ++d) {
-                        jv[d] = -1;
-                        tv[d] = 0.0;
                         const int pp = base + d * G + lane;
-                        if (pp < total) {
-                            int lo = 0, hi = G - 1;   // largest e with poff[e] <= pp
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (poff[mid] <= pp) lo = mid; else hi = mid - 1;
-                            }
-                            const int4 pr = par[lo];
-                            const int q = pr.x + (pp - poff[lo]);
-                            jv[d] = bci[q];
-                            tv[d] = __hiloint2double(pr.w, pr.z) * bval[q];
+                        int lo = -1, po = 0;
+#pragma unroll
+                        for (int x = 0; x < G; ++x) {
+                            const bool le = pofv[x] <= pp;
+                            lo += le ? 1 : 0;
+                            po = le ? pofv[x] : po;
                         }
+                        const int4 pr = par[lo];
+                        const int q = pr.x + (pp - po);
+                        const bool ok = pp < total;
+                        const MLS_G int32_t *pj = ok ? bci + q : (const MLS_G int32_t *)k_num_void;
+                        const MLS_G double *pv = ok ? bval + q : (const MLS_G double *)k_num_void;
+                        jv[d] = *pj;
+                        bv[d] = *pv;
+                        av[d] = __hiloint2double(pr.w, pr.z);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                     int posv[kNumDepth];
                     tab.template lookup_n<kNumDepth>(logcap, jv, posv);
+#pragma unroll
+                    for (int d = 0; d < kNumDepth; ++d) asm volatile("" ::"v"(bv[d]));
 #pragma unroll
                     for (int d = 0; d < kNumDepth; ++d)
                         if (posv[d] == -1) bad = true;
@@ -445,9 +461,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
                     // effect in program order
 #pragma unroll
                     for (int d = 0; d < kNumDepth; ++d) {
-                        const int rk = posv[d] >= 0 ? group_rank<G>(posv[d], lane) : -1;
+                        const int rank = group_rank<G>(posv[d], lane);
+                        const int rk = posv[d] >= 0 ? rank : -1;
+                        const double t = av[d] * bv[d];
                         for (int rr = 0;; ++rr) {
-                            if (rk == rr) atomicAdd(acc + posv[d], tv[d]);
+                            if (rk == rr) atomicAdd(acc + posv[d], t);
                             if (!__ballot(rk > rr)) break;
                         }
                     }
