@@ -26,6 +26,9 @@ namespace mls {
 
 constexpr int kBwdUnroll = 4;
 
+// all ones: read as a column it is -1 (no entry)
+__device__ __attribute__((aligned(8))) int32_t k_bwd_void[2] = {-1, -1};
+
 __device__ __forceinline__ void bwd_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -100,7 +103,7 @@ __device__ __forceinline__ void w_lookup_n(const int *key, const double *wv, int
 
 // LDS of one row: W_i's hash (key, value), the staged entries of A (first B
 // position, a_ik, their dA sums) and the staged entries' first pairs
-constexpr int bwd_row_bytes(int CAP, int G) { return CAP * 12 + G * 20 + (G + 1) * 4; }
+constexpr int bwd_row_bytes(int CAP, int G) { return CAP * 12 + G * 20 + (G + 4) * 4; }
 
 // Waves per workgroup that keep the most waves resident on a CU (160 KB of
 // LDS, 32 waves), given the LDS of one wave.
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
     __shared__ double s_pa[NW * W * G];
     __shared__ double s_da[NW * W * G];
     __shared__ int s_pq[NW * W * G];
-    __shared__ int s_poff[NW * W * (G + 1)];
+    __shared__ __attribute__((aligned(16))) int s_poff[NW * W * (G + 4)];   // read four at a time
 
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
     double *pa = s_pa + rs * G;
     double *da = s_da + rs * G;
     int *pq = s_pq + rs * G;
-    int *poff = s_poff + rs * (G + 1);
+    int *poff = s_poff + rs * (G + 4);
 
     const Prob P = b.p0;
     const MLS_G int32_t *__restrict__ aci = gp(P.aci);
@@ -243,28 +246,58 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
             pa[lane] = a;
             da[lane] = 0.0;
             bwd_sync();
+            // groups of at most 16 lanes keep the pair offsets in registers: a
+            // pair's entry is the last one whose offset is at most its index
+            constexpr int RG = G <= 16 ? G : 4;
+            int pofv[RG];
+            if constexpr (G <= 16) {
+#pragma unroll
+                for (int x = 0; x < G; x += 4) {
+                    const int4 v = *(const int4 *)(poff + x);
+                    pofv[x] = v.x; pofv[x + 1] = v.y; pofv[x + 2] = v.z; pofv[x + 3] = v.w;
+                }
+            }
             for (int base = 0; base < total; base += G * kBwdUnroll) {
                 int qv[kBwdUnroll], ev[kBwdUnroll], jv[kBwdUnroll];
                 double bv[kBwdUnroll];
+                // loads without branches (pairs past the chunk read the all-ones
+                // dummy: column -1), all issued before any use
 #pragma unroll
                 for (int d = 0; d < kBwdUnroll; ++d) {
-                    jv[d] = -1; qv[d] = 0; ev[d] = 0; bv[d] = 0.0;
                     const int pp = base + d * G + lane;
-                    if (pp < total) {
-                        int lo = 0, hi = G - 1;   // largest e with poff[e] <= pp
+                    int lo, po;
+                    if constexpr (G <= 16) {
+                        lo = -1;
+                        po = 0;
+#pragma unroll
+                        for (int x = 0; x < G; ++x) {
+                            const bool le = pofv[x] <= pp;
+                            lo += le ? 1 : 0;
+                            po = le ? pofv[x] : po;
+                        }
+                    } else {
+                        lo = 0;
+                        int hi = G - 1;   // largest e with poff[e] <= pp
                         while (lo < hi) {
                             const int mid = (lo + hi + 1) >> 1;
                             if (poff[mid] <= pp) lo = mid; else hi = mid - 1;
                         }
-                        ev[d] = lo;
-                        qv[d] = pq[lo] + (pp - poff[lo]);
-                        jv[d] = bci[qv[d]];
-                        bv[d] = bval[qv[d]];
+                        po = poff[lo];
                     }
+                    const bool ok = pp < total;
+                    ev[d] = lo;
+                    qv[d] = pq[lo] + (pp - po);
+                    const MLS_G int32_t *pj = ok ? bci + qv[d] : (const MLS_G int32_t *)k_bwd_void;
+                    const MLS_G double *pv = ok ? bval + qv[d] : (const MLS_G double *)k_bwd_void;
+                    jv[d] = *pj;
+                    bv[d] = *pv;
                 }
+                __builtin_amdgcn_sched_barrier(0);
                 int sl[kBwdUnroll];
                 double w[kBwdUnroll];
                 w_lookup_n<kBwdUnroll>(key, wv, logcap, jv, sl, w);
+#pragma unroll
+                for (int d = 0; d < kBwdUnroll; ++d) asm volatile("" ::"v"(bv[d]));
 #pragma unroll
                 for (int d = 0; d < kBwdUnroll; ++d) {
                     if (sl[d] == -1) bad = true;
