@@ -68,8 +68,33 @@ struct PackBits {
     static constexpr uint32_t kMaxCols = (1u << (32 - PB)) - 1u;   // columns < this fit
 };
 
-template <int CAP, bool PACK>
+// Bucket words of a packed table: BK = 2 or 4 slots read in one LDS access.
+template <int BK> struct BucketT;
+template <> struct BucketT<2> {
+    using T = uint2;
+    __device__ __forceinline__ static uint32_t minx(T w, uint32_t k) { return min(w.x ^ k, w.y ^ k); }
+    __device__ __forceinline__ static uint32_t last(T w) { return w.y; }
+    __device__ __forceinline__ static int first_empty(T w, uint32_t e) { return w.x == e ? 0 : (w.y == e ? 1 : 2); }
+};
+template <> struct BucketT<4> {
+    using T = uint4;
+    __device__ __forceinline__ static uint32_t minx(T w, uint32_t k)
+    {
+        return min(min(w.x ^ k, w.y ^ k), min(w.z ^ k, w.w ^ k));
+    }
+    __device__ __forceinline__ static uint32_t last(T w) { return w.w; }
+    __device__ __forceinline__ static int first_empty(T w, uint32_t e)
+    {
+        return w.x == e ? 0 : (w.y == e ? 1 : (w.z == e ? 2 : (w.w == e ? 3 : 4)));
+    }
+};
+
+template <int CAP, bool PACK, int BK = 4>
 struct PosTab {
+    static_assert(BK == 2 || BK == 4, "bucket of 2 or 4 slots");
+    using BT = BucketT<BK>;
+    using BW = typename BT::T;
+    static constexpr int LB = BK == 2 ? 1 : 2;   // log2 of the bucket width
     uint32_t *t;   // CAP words (packed) or 2*CAP words (wide)
 
     __device__ __forceinline__ void clear(int cap, int lane, int G)
@@ -88,16 +113,16 @@ struct PosTab {
 
     static constexpr uint32_t kEmpty = 0xffffffffu;
 
-    // Packed tables are probed a bucket (4 slots, 16 bytes) at a time: a key
+    // Packed tables are probed a bucket (BK slots, one LDS read) at a time: a key
     // takes the first empty slot at or after the start of its home bucket, so
     // the filled slots of every bucket are a prefix of it (a lane only claims
     // a slot after seeing every earlier one taken, and slots are never
     // emptied), and a bucket whose last slot is empty ends a search.
     __device__ __forceinline__ static uint32_t home(int logcap, int j)
     {
-        return hslot((uint32_t)j, logcap - 2) << 2;
+        return hslot((uint32_t)j, logcap - LB) << LB;
     }
-    __device__ __forceinline__ uint4 bucket(uint32_t h) const { return *(const uint4 *)(t + h); }
+    __device__ __forceinline__ BW bucket(uint32_t h) const { return *(const BW *)(t + h); }
 
     __device__ __forceinline__ void insert(int logcap, int j, int pos)
     {
@@ -105,12 +130,11 @@ struct PosTab {
         if (PACK) {
             const uint32_t v = ((uint32_t)j << PackBits<CAP>::PB) | (uint32_t)pos;
             uint32_t h = home(logcap, j);
-            for (uint32_t probe = 0; probe <= cmask; probe += 4) {
-                const uint4 w = bucket(h);
-                int sl = w.x == kEmpty ? 0 : (w.y == kEmpty ? 1 : (w.z == kEmpty ? 2 : (w.w == kEmpty ? 3 : 4)));
-                for (; sl < 4; ++sl)
+            for (uint32_t probe = 0; probe <= cmask; probe += BK) {
+                int sl = BT::first_empty(bucket(h), kEmpty);
+                for (; sl < BK; ++sl)
                     if (atomicCAS(t + h + sl, kEmpty, v) == kEmpty) return;
-                h = (h + 4u) & cmask;
+                h = (h + BK) & cmask;
             }
         } else {
             uint32_t h = hslot((uint32_t)j, logcap);
@@ -127,13 +151,13 @@ struct PosTab {
     // -1 when j is not in the row. A slot holds j iff its word XOR (j << PB)
     // is below 2^PB, and that value is then the position; at most one slot
     // of a bucket holds j, so the minimum over the bucket decides.
-    __device__ __forceinline__ int find(int logcap, int j, uint32_t h, uint4 w, bool live = true) const
+    __device__ __forceinline__ int find(int logcap, int j, uint32_t h, BW w, bool live = true) const
     {
         constexpr int PB = PackBits<CAP>::PB;
         const uint32_t key = (uint32_t)j << PB, pm = (1u << PB) - 1u;
-        const uint32_t m = min(min(w.x ^ key, w.y ^ key), min(w.z ^ key, w.w ^ key));
+        const uint32_t m = BT::minx(w, key);
         int p = m <= pm ? (int)m : -1;
-        if (live && m > pm && w.w != kEmpty) p = find_more(logcap, key, h);
+        if (live && m > pm && BT::last(w) != kEmpty) p = find_more(logcap, key, h);
         return p;
     }
 
@@ -142,12 +166,12 @@ struct PosTab {
     {
         constexpr int PB = PackBits<CAP>::PB;
         const uint32_t pm = (1u << PB) - 1u, cmask = (1u << logcap) - 1u;
-        for (uint32_t probe = 4; probe <= cmask; probe += 4) {
-            h = (h + 4u) & cmask;
-            const uint4 v = bucket(h);
-            const uint32_t mv = min(min(v.x ^ key, v.y ^ key), min(v.z ^ key, v.w ^ key));
+        for (uint32_t probe = BK; probe <= cmask; probe += BK) {
+            h = (h + BK) & cmask;
+            const BW v = bucket(h);
+            const uint32_t mv = BT::minx(v, key);
             if (mv <= pm) return (int)mv;
-            if (v.w == kEmpty) return -1;
+            if (BT::last(v) == kEmpty) return -1;
         }
         return -1;
     }
@@ -183,7 +207,7 @@ struct PosTab {
 #pragma unroll
             for (int d0 = 0; d0 < D; d0 += 2) {
                 uint32_t hv[2];
-                uint4 wv[2];
+                BW wv[2];
 #pragma unroll
                 for (int d = 0; d < 2; ++d) hv[d] = jv[d0 + d] >= 0 ? home(logcap, jv[d0 + d]) : 0u;
 #pragma unroll
@@ -210,8 +234,8 @@ struct PosTab {
 template <int G>
 constexpr int ins_depth() { return G >= 32 ? 2 : 4; }
 
-template <int G, int CAP, bool PACK>
-__device__ __forceinline__ void insert_row(PosTab<CAP, PACK> &tab, double *acc, int logcap,
+template <int G, typename TAB>
+__device__ __forceinline__ void insert_row(TAB &tab, double *acc, int logcap,
                                            const MLS_G int32_t *__restrict__ cols,
                                            const MLS_G double *__restrict__ vals, int off, int n, int lane,
                                            bool accumulate)
@@ -342,7 +366,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
     const int lw = threadIdx.x & 63;
     const int slot = lw / G, lane = lw % G;
     const int rs = wave * W + slot;
-    PosTab<CAP, PACK> tab{s_tab + rs * TW};
+    // 2-slot buckets where 32 or more lanes own a row (measured on the
+    // 27-point stencil square), 4-slot ones for narrower groups
+    PosTab<CAP, PACK, (G >= 32 ? 2 : 4)> tab{s_tab + rs * TW};
     double *acc = s_acc + rs * (CAP / 2);
     int4 *par = s_par + rs * G;
     int *poff = (int *)(s_tab + NW * W * TW) + rs * XW;   // FLAT only: staged pair offsets
@@ -388,7 +414,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
         double sa = 0.0;
         if (ps + lane < pe) { ka = aci[ps + lane]; sa = aval[ps + lane]; }
         nwave_sync();
-        insert_row<G, CAP, PACK>(tab, acc, logcap, cci, cval, cs, nc, lane, accumulate);
+        insert_row<G>(tab, acc, logcap, cci, cval, cs, nc, lane, accumulate);
         m = row_meta<MULTI>(b, sc, act_n, g_n, pc);
         nwave_sync();
         bool bad = false;
@@ -624,7 +650,7 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
     const int wave = threadIdx.x >> 6;
     if (wave >= NW) return;
     const int lane = threadIdx.x & 63;
-    PosTab<CAP, PACK> tab{s_tab + wave * TW};
+    PosTab<CAP, PACK, 2> tab{s_tab + wave * TW};
     double *acc = s_acc + wave * M;
     int4 *par = s_par + wave * G;
     int *poff = s_poff + wave * (G + 1);
@@ -687,7 +713,7 @@ __global__ __launch_bounds__(kWG) void k_num_win(Batch b, Sched sc)
             if (logcap < 5) logcap = 5;
             tab.clear(1 << logcap, lane, G);
             nwave_sync();
-            insert_row<G, CAP, PACK>(tab, acc, logcap, cci, cval, cs, n, lane, accumulate);
+            insert_row<G>(tab, acc, logcap, cci, cval, cs, n, lane, accumulate);
             nwave_sync();
             bool bad = false;
             for (int pc = ps; pc < pe; pc += G) {
