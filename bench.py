@@ -334,7 +334,10 @@ def bench_headline(torch, mls, synth, args, keep_host, parity):
                      "compulsory_bytes": compulsory, "compulsory_frac": frac(compulsory, dom_ms),
                      "traffic_frac": frac(traffic, dom_ms) if traffic else None,
                      "numeric_phase_kernels_ms": round(num_ms, 4),
-                     "numeric_phase_traffic_frac": frac(traffic, num_ms) if traffic else None},
+                     "numeric_phase_traffic_frac": frac(traffic, num_ms) if traffic else None,
+                     "note": ("model rate above the HBM peak: L2 and MALL reuse serve the gathered rows of B; "
+                              "traffic_frac is the counter-measured HBM-side fraction")
+                     if achieved > HBM_PEAK_GBS else None},
         "kernels": kernel_dict(prof, preps),
     }
     host = None
