@@ -214,23 +214,49 @@ void k_sym_lds(Batch b, Sched sc, int bin)
         int pre_k = -1;
         if (m.g >= 0 && m.ps + lane < m.pe) pre_k = gp(get_prob(b, m.t).aci)[m.ps + lane];
         if (!FILL) {
-            // popcount of the union and number of occupied slots; each lane owns
-            // 4 (vec) or 1 consecutive slots per pass
+            // one pass over the table: popcount of the union, and the occupied
+            // (set, mask) words compacted in slot order into the row's scratch
+            // slot for the fill pass (the first kScratchWords of them; a row
+            // with more is marked and rebuilt there); each lane owns 4 (vec)
+            // or 1 consecutive slots per step
             const int per = vec ? 4 : 1;
-            int c = 0, nsets = 0;
-            for (int h = per * lane; h < cap; h += per * G) {
-                if (vec) {
-                    const uint4 k4 = *(const uint4 *)(key + h);
-                    const uint4 m4 = *(const uint4 *)(msk + h);
-                    c += __popc(m4.x) + __popc(m4.y) + __popc(m4.z) + __popc(m4.w);
-                    nsets += (k4.x != kEmptyKey) + (k4.y != kEmptyKey) + (k4.z != kEmptyKey) + (k4.w != kEmptyKey);
-                } else {
-                    c += __popc(msk[h]);
-                    nsets += key[h] != kEmptyKey;
+            MLS_G u32x2 *dst = (MLS_G u32x2 *)sc.scr + (int64_t)g * kScratchWords;
+            int c = 0, base = 0;
+            for (int h0 = 0; h0 < cap; h0 += per * G) {
+                const int h = h0 + per * lane;
+                uint32_t kk[4], mm[4];
+                int nl = 0;
+                if (h < cap) {
+                    if (vec) {
+                        const uint4 k4 = *(const uint4 *)(key + h);
+                        const uint4 m4 = *(const uint4 *)(msk + h);
+                        kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
+                        mm[0] = m4.x; mm[1] = m4.y; mm[2] = m4.z; mm[3] = m4.w;
+                    } else {
+                        kk[0] = key[h]; mm[0] = msk[h];
+                    }
+                    for (int x = 0; x < per; ++x) {
+                        nl += kk[x] != kEmptyKey;
+                        c += __popc(mm[x]);
+                    }
                 }
+                // exclusive prefix of nl over the group
+                const int incl = group_scan_incl<G>(nl, lane);
+                const int tot = group_total<G>(nl, incl);
+                if (sc.scr && active && nl) {
+                    int w = base + incl - nl;
+                    for (int x = 0; x < per; ++x)
+                        if (kk[x] != kEmptyKey) {
+                            if (w < kScratchWords) {
+                                u32x2 v; v.x = kk[x]; v.y = mm[x];
+                                dst[w] = v;
+                            }
+                            ++w;
+                        }
+                }
+                base += tot;
             }
             c = group_sum<G>(c);
-            nsets = group_sum<G>(nsets);
             if (pre_k >= 0) {
                 const Prob Pn = get_prob(b, m.t);
                 if (pre_k >= Pn.k_lo && pre_k < Pn.k_hi) {
@@ -238,43 +264,9 @@ void k_sym_lds(Batch b, Sched sc, int bin)
                     pre_nw = gp(Pn.bwc)[pre_k - Pn.k_lo];
                 }
             }
-            if (active && lane == 0) val[g] = c;
-            if (sc.scr) {
-                // keep the row's words for the fill pass (compacted in slot order)
-                const bool fits = nsets <= kScratchWords;
-                if (active && lane == 0) gpw(sc.scnt)[g] = fits ? nsets : -1;
-                if (fits) {
-                    MLS_G u32x2 *dst = (MLS_G u32x2 *)sc.scr + (int64_t)g * kScratchWords;
-                    int base = 0;
-                    for (int h0 = 0; h0 < cap; h0 += per * G) {
-                        const int h = h0 + per * lane;
-                        uint32_t kk[4], mm[4];
-                        int nl = 0;
-                        if (h < cap) {
-                            if (vec) {
-                                const uint4 k4 = *(const uint4 *)(key + h);
-                                const uint4 m4 = *(const uint4 *)(msk + h);
-                                kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
-                                mm[0] = m4.x; mm[1] = m4.y; mm[2] = m4.z; mm[3] = m4.w;
-                            } else {
-                                kk[0] = key[h]; mm[0] = msk[h];
-                            }
-                            for (int x = 0; x < per; ++x) nl += kk[x] != kEmptyKey;
-                        }
-                        // exclusive prefix of nl over the group
-                        int incl = group_scan_incl<G>(nl, lane);
-                        const int tot = group_total<G>(nl, incl);
-                        if (active && nl) {
-                            int w = base + incl - nl;
-                            for (int x = 0; x < per; ++x)
-                                if (kk[x] != kEmptyKey) {
-                                    u32x2 v; v.x = kk[x]; v.y = mm[x];
-                                    dst[w++] = v;
-                                }
-                        }
-                        base += tot;
-                    }
-                }
+            if (active && lane == 0) {
+                val[g] = c;
+                if (sc.scr) gpw(sc.scnt)[g] = base <= kScratchWords ? base : -1;
             }
         } else {
             if (pre_k >= 0) {
