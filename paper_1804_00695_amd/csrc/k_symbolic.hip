@@ -177,11 +177,19 @@ void k_sym_lds(Batch b, Sched sc, int bin)
                     nw = bwc[kl];
                 }
                 const MLS_G u32x2 *w = bw + q0;
+                // each lane starts at its own word of the row and wraps around:
+                // neighbouring rows of B share most sets, and lanes ORing the same
+                // set in one instruction would be serialized by the LDS
+                const int rot = nw > 0 ? lane % nw : 0;
                 for (int x = 0; x < nw; x += SB) {
                     u32x2 wd[SB];
 #pragma unroll
                     for (int d = 0; d < SB; ++d)
-                        if (x + d < nw) wd[d] = w[x + d];
+                        if (x + d < nw) {
+                            int e = x + d + rot;
+                            if (e >= nw) e -= nw;
+                            wd[d] = w[e];
+                        }
                     // the home slots of all the words are read before any is
                     // updated, so their LDS latencies overlap
                     uint32_t hv[SB], kv[SB];
