@@ -494,11 +494,20 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
             const MLS_G int32_t *__restrict__ brp = gp(P.brp);
             const MLS_G int32_t *__restrict__ bwc = gp(P.bwc);
             const int k_lo = P.k_lo, k_hi = P.k_hi;
-            for (int p = s + lane; p < e; p += kBinRG) {
-                const int k = aci[p];
-                if (k < k_lo || k >= k_hi) continue;
-                const int kl = k - k_lo;
-                size += mode == kModeWork ? (int64_t)(brp[kl + 1] - brp[kl]) : (int64_t)bwc[kl];
+            // four entries per lane in flight: their columns, then the gathers
+            for (int p0 = s + lane; p0 < e; p0 += 4 * kBinRG) {
+                int kv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int p = p0 + u * kBinRG;
+                    kv[u] = p < e ? aci[p] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (kv[u] < k_lo || kv[u] >= k_hi) continue;
+                    const int kl = kv[u] - k_lo;
+                    size += mode == kModeWork ? (int64_t)(brp[kl + 1] - brp[kl]) : (int64_t)bwc[kl];
+                }
             }
             size = group_sum<kBinRG>(size);
         }
