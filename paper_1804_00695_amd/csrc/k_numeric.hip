@@ -12,8 +12,9 @@
 // lanes of a step touch the same accumulator and every c_ij receives its
 // terms in ascending k -- the order of the row-wise formulation. Products are
 // rounded before the add (compiled without contraction), so the result equals
-// a sequential dense-accumulator evaluation bit for bit. Loads for U entries
-// of A are issued before their accumulation steps to hide HBM/L2 latency.
+// a sequential dense-accumulator evaluation bit for bit. The B loads of a
+// batch of steps are all issued, without branches, before the first of them
+// is used, to hide HBM/L2 latency.
 //
 // Spill path (rows with more outputs than the largest LDS class holds): the
 // row's outputs are cut into windows of consecutive positions of C, each a
