@@ -510,6 +510,7 @@ spgemm_status run_chunked(const spgemm_csr *A, const spgemm_csr *B, const spgemm
             q.b_off = B->row_ptr[bq.r0];
             q.k_lo = bq.r0;
             q.k_hi = bq.r1;
+            q.ranged = (bq.r0 > 0 || bq.r1 < B->nrows) ? 1 : 0;
             const bool first = !binned[stp.part];
             if (tr) {
                 tr->begin();

@@ -59,7 +59,9 @@ struct Prob {
     int32_t a_off, b_off, c_off;
     int32_t k_lo, k_hi;     // A columns outside [k_lo, k_hi) are skipped
     int32_t accumulate;     // numeric: 1 = add onto the values already in C
-    int32_t pad;
+    int32_t ranged;         // numeric: [k_lo, k_hi) is part of B's rows; a row of at most one
+                            // chunk with no entry in it is skipped (its values stay, or are
+                            // set to 0 when not accumulating)
 };
 
 static_assert(sizeof(Prob) % 16 == 0, "Prob is copied in 16-byte words");

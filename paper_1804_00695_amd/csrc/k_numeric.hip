@@ -414,12 +414,21 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
         int ka = -1;
         double sa = 0.0;
         if (ps + lane < pe) { ka = aci[ps + lane]; sa = aval[ps + lane]; }
+        // a step over a part of B's rows skips the rows (of one chunk) with no
+        // entry in it: most rows of A reach only a few parts
+        bool skip = false;
+        if (P.ranged) {
+            const unsigned long long bal = __ballot(ka >= k_lo && ka < k_hi);
+            const unsigned long long gm = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (slot * G);
+            skip = active && pe - ps <= G && (bal & gm) == 0ull;
+        }
         nwave_sync();
-        insert_row<G>(tab, acc, logcap, cci, cval, cs, nc, lane, accumulate);
+        if (!skip) insert_row<G>(tab, acc, logcap, cci, cval, cs, nc, lane, accumulate);
         m = row_meta<MULTI>(b, sc, act_n, g_n, pc);
         nwave_sync();
         bool bad = false;
-        for (int pc = ps; pc < pe; pc += G) {
+        const int pe_w = skip ? ps : pe;
+        for (int pc = ps; pc < pe_w; pc += G) {
             // stage the chunk: (q0, q1, a) of entry pc + lane
             int sq0 = 0, sq1 = 0;
             if (ka >= k_lo && ka < k_hi) {
@@ -561,8 +570,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
             nwave_sync();
         }
         if (bad) atomicOr(sc.err, kErrStructure);
-        if (active)
+        if (active && !skip)
             for (int e = lane; e < nc; e += G) cval[cs + e] = acc[e];
+        else if (active && !accumulate)
+            for (int e = lane; e < nc; e += G) cval[cs + e] = 0.0;
         nwave_sync();
         task = task_n;
     }
