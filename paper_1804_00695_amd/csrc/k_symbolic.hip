@@ -228,7 +228,7 @@ void k_sym_lds(Batch b, Sched sc, int bin)
             // with more is marked and rebuilt there); each lane owns 4 (vec)
             // or 1 consecutive slots per step
             const int per = vec ? 4 : 1;
-            MLS_G u32x2 *dst = (MLS_G u32x2 *)sc.scr + (int64_t)g * kScratchWords;
+            MLS_G u32x2 *dst = sc.scr ? (MLS_G u32x2 *)sc.scr + (int64_t)g * kScratchWords : nullptr;
             int c = 0, base = 0;
             for (int h0 = 0; h0 < cap; h0 += per * G) {
                 const int h = h0 + per * lane;
