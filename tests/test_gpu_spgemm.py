@@ -410,3 +410,48 @@ def test_forced_class(cls):
     B = synth.random_csr(150, 120, 0.05, 4, empty_rows=0.5)
     check(A, B)
     check(wide_rows(24, 3000, 120, 11), synth.poisson_csr(3000, 9000, 8.0, 12))
+
+
+def colliding_columns(count, bits, target, ncols):
+    """Columns whose multiplicative hash (the LDS tables' key -> slot map,
+    column * 0x9E3779B1 mod 2^32, top bits) has the given top `bits` bits:
+    they all share one home bucket, so inserts and lookups run through the
+    probing past full buckets."""
+    j = np.arange(ncols, dtype=np.uint64)
+    top = ((j * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - bits)
+    cols = np.nonzero(top == target)[0]
+    assert len(cols) >= count
+    return cols[:count].astype(np.int32)
+
+
+def colliding_instance(per_row, bits, seed):
+    g = synth.rng(seed)
+    ncols = 1 << 16
+    fam = colliding_columns(3 * per_row, bits, 5, ncols)
+    kb = 48
+    rows = [np.sort(g.choice(fam, per_row, replace=False)) for _ in range(kb)]
+    brp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    B = synth.Csr(kb, ncols, brp, np.concatenate(rows).astype(np.int32), synth.normal_values(int(brp[-1]), seed + 1))
+    m = 40
+    arows = [np.sort(g.choice(kb, 3, replace=False)) for _ in range(m)]
+    arp = np.arange(0, 3 * m + 1, 3, dtype=np.int32)
+    A = synth.Csr(m, kb, arp, np.concatenate(arows).astype(np.int32), synth.normal_values(3 * m, seed + 2))
+    return A, B
+
+
+@pytest.mark.parametrize("group", [0, 8, 16, 32, 64])
+@pytest.mark.parametrize("per_row,bits", [(20, 7), (40, 8)])
+@pytest.mark.parametrize("wide", [0, 1])
+def test_hash_bucket_overflow(group, per_row, bits, wide):
+    # rows of C of 40-120 columns, all with one home bucket in their table
+    # (2- and 4-slot buckets alike): bit-exact values, and the adjoint too
+    A, B = colliding_instance(per_row, bits, 31 + per_row)
+    mls.set_option(mls._abi.OPT_GROUP_SIZE, group)
+    mls.set_option(mls._abi.OPT_WIDE_TABLE, wide)
+    R = check(A, B)
+    W = synth.Csr(R.nrows, R.ncols, R.row_ptr, R.col_idx, synth.normal_values(R.nnz, 7))
+    dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W))
+    torch.cuda.synchronize()
+    rA, rB, aA, aB = oracle.backward(A, B, W)
+    assert np.all(np.abs(dA.cpu().numpy() - rA) <= 1e-10 * aA + 1e-300)
+    assert np.all(np.abs(dB.cpu().numpy() - rB) <= 1e-10 * aB + 1e-300)
