@@ -33,7 +33,7 @@ constexpr uint32_t kErrTable = 8u;
 //   count  : threshold on the word upper bound u, table = u slots at most
 //   fill / numeric : threshold on the exact size n, table >= 2n slots
 // (triangle counting keeps a table of its own, on the same rule)
-constexpr int kCountCap[kNumClasses] = {128, 256, 512, 2048, 8192};
+constexpr int kCountCap[kNumClasses] = {64, 256, 512, 2048, 8192};
 constexpr int kFillCap[kNumClasses] = {64, 256, 1024, 2048, 4096};
 
 struct Prob {

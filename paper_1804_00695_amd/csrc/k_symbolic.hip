@@ -25,7 +25,7 @@ constexpr uint32_t kEmptyKey = 0xffffffffu;
 constexpr int kSymBatch = 6;   // words of one B_k row loaded before they are inserted (measured)
 // fewer where 32 or more lanes own a row (their count kernels run at 6 waves per SIMD)
 template <int G, bool FILL>
-constexpr int sym_batch() { return (!FILL && G >= 32) ? 4 : kSymBatch; }
+constexpr int sym_batch() { return (!FILL && (G >= 32 || G <= 8)) ? 4 : kSymBatch; }
 
 __device__ __forceinline__ void wave_sync()
 {
