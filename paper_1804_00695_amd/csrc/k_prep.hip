@@ -551,9 +551,13 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
 // (bins in order, blocks in order inside a bin). Only the nb blocks of this
 // launch count: a launch over fewer rows than the workspace was laid out for
 // (a chunk part) leaves the counts of later blocks from earlier launches.
-__global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
+// The bin scan runs as one workgroup of 1024 threads, 8192 blocks of counts
+// per step (a batch of 22M rows has 21.5K blocks per bin)
+constexpr int kScanWG = 1024;
+
+__global__ __launch_bounds__(kScanWG) void k_bin_scan(Sched sc, int nb)
 {
-    __shared__ int64_t s_red[kWG / kWave];
+    __shared__ int64_t s_red[kScanWG / kWave];
     __shared__ int64_t s_start[kNumBins];
     __shared__ int64_t s_carry;
     MLS_G int32_t *blk = gpw(sc.blk_cnt);
@@ -566,8 +570,8 @@ __global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
     // bins in order, the running position spanning them: every block's count
     // becomes the position in perm where its rows of the bin start; a bin's
     // total is the difference of the positions where it and the next begin.
-    // With at most kWG * kPer blocks, all bins' counts are loaded up front.
-    const bool one_step = nblk <= kWG * kPer;
+    // With at most kScanWG * kPer blocks, all bins' counts are loaded up front.
+    const bool one_step = nblk <= kScanWG * kPer;
     int32_t pre[kNumBins][kPer];
     if (one_step) {
         const int xb = threadIdx.x * kPer;
@@ -579,7 +583,7 @@ __global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
 #pragma unroll
     for (int c = 0; c < kNumBins; ++c) {
         if (threadIdx.x == 0) s_start[c] = s_carry;
-        for (int x0 = 0; x0 < nblk; x0 += kWG * kPer) {
+        for (int x0 = 0; x0 < nblk; x0 += kScanWG * kPer) {
             const int xb = x0 + threadIdx.x * kPer;
             int32_t v[kPer];
             int64_t sum = 0;
@@ -606,7 +610,7 @@ __global__ __launch_bounds__(kWG) void k_bin_scan(Sched sc, int nb)
             __syncthreads();
             if (threadIdx.x == 0) {
                 int64_t t = 0;
-                for (int w = 0; w < kWG / kWave; ++w) t += s_red[w];
+                for (int w = 0; w < kScanWG / kWave; ++w) t += s_red[w];
                 s_carry += t;
             }
             __syncthreads();
@@ -804,7 +808,7 @@ void launch_scatter(int na, const Sched &sc, hipStream_t s)
     if (na <= 0) return;
     ProfScope ps("scatter", s);
     const int nb = nblk(na, kBinRowsPerWG);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kWG), 0, s, sc, nb);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kScanWG), 0, s, sc, nb);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kWG), 0, s, na, sc);
 }
 
