@@ -34,12 +34,12 @@ namespace mls {
 
 constexpr int kNumDepth = 4;   // steps whose B loads are issued together (8 where LDS caps occupancy at 4)
 constexpr int kNumWinCap = 1024;   // table slots of a spill window (CAP / 2 positions)
-constexpr int kWinDepth = 2;
+constexpr int kWinDepth = 2;       // spill window: batches of 64 pairs whose B loads are issued together
 constexpr bool kNumFlat = true;    // flattened pairs for the classes of at most kNumFlatMaxG lanes per row
 constexpr int kNumFlatMaxG = 8;
 
 // all ones: read as a column it is -1 (no entry)
-__device__ __attribute__((aligned(8))) int32_t k_num_void[2] = {-1, -1};       // spill window: batches of 64 pairs whose B loads are issued together
+__device__ __attribute__((aligned(8))) int32_t k_num_void[2] = {-1, -1};
 
 __device__ __forceinline__ void nwave_sync()
 {
@@ -286,11 +286,11 @@ constexpr int num_row_bytes(int CAP, int G, bool PACK)
     return CAP * (PACK ? 4 : 8) + (CAP / 2) * 8 + G * 16;
 }
 
-// Where a row of the bin lives: product t, local row i, output size nc, the
-// start of its C entries (cs) and its A entry range [ps, pe), all local.
+// Where a row of the bin lives: product t, output size nc, the start of its
+// C entries (cs) and its A entry range [ps, pe), all local (a slot without a
+// row: nc = 0 and an empty range).
 struct RowMeta {
     int t, nc, cs, ps, pe;
-    bool active;
 };
 
 // The descriptor of product t: the kernel argument for a single product (its
@@ -302,22 +302,98 @@ __device__ __forceinline__ Prob prob_of(const Batch &b, int t)
     return get_prob(b, t);
 }
 
-template <bool MULTI>
-__device__ __forceinline__ RowMeta row_meta(const Batch &b, const Sched &sc, bool active, int g, ProbCache &pc)
+// Rows are software-pipelined across loop iterations, and every load of that
+// pipeline is issued without a branch around it (a lane with nothing to load
+// reads a constant word instead), so its first use can sit a row or more
+// behind it: a use inside a branch would make the wave wait at the branch.
+
+// zero words: the target of such loads for row pointers and values
+__device__ __attribute__((aligned(16))) int32_t k_num_zero[4] = {0, 0, 0, 0};
+
+// Row at position pos of the bin (when want): the perm load is only issued;
+// bin_row_checked validates the value where it is first used. A position
+// outside the batch never comes from consistent bins and is flagged.
+__device__ __forceinline__ int bin_row_issue(const int32_t *perm, uint32_t *err, int na, int pos, bool want)
 {
-    RowMeta m{0, 0, 0, 0, 0, active};
-    if (!active) return m;
+    const bool ok = want && (unsigned)pos < (unsigned)na;
+    if (want && !ok) atomicOr(err, kErrTable);
+    return *(ok ? gp(perm) + pos : (const MLS_G int32_t *)k_num_void);
+}
+
+__device__ __forceinline__ int bin_row_checked(uint32_t *err, int na, int g, bool want)
+{
+    if (!want) return -1;
+    if ((unsigned)g >= (unsigned)na) { atomicOr(err, kErrTable); return -1; }
+    return g;
+}
+
+// A row's metadata as loaded: output size and row pointers before their
+// offsets are subtracted (row_final), product t for a batch. A slot with no
+// row reads zeros: no outputs and an empty range of A, so every step of the
+// row loop is empty for it.
+struct RowRaw {
+    int t, nc, c0, a0, a1;
+};
+
+template <bool MULTI>
+__device__ __forceinline__ RowRaw row_issue(const Batch &b, const Sched &sc, int g, ProbCache &pc)
+{
+    RowRaw r{0, 0, 0, 0, 0};
+    const bool on = g >= 0;
     int i = g;
-    if (MULTI) {
-        m.t = find_prob_cached(b.abase, b.nprob, g, pc);
+    if (MULTI && on) {
+        r.t = find_prob_cached(b.abase, b.nprob, g, pc);
         i = g - pc.lo;
     }
-    const Prob P = prob_of<MULTI>(b, m.t);
-    m.nc = gp(sc.val)[g];
-    m.cs = gp(P.crp)[i] - P.c_off;
-    m.ps = gp(P.arp)[i] - P.a_off;
-    m.pe = gp(P.arp)[i + 1] - P.a_off;
+    const Prob P = prob_of<MULTI>(b, r.t);
+    const MLS_G int32_t *zero = (const MLS_G int32_t *)k_num_zero;
+    const MLS_G int32_t *pv = on ? gp(sc.val) + g : zero;
+    const MLS_G int32_t *pcr = on ? gp(P.crp) + i : zero;
+    const MLS_G int32_t *par = on ? gp(P.arp) + i : zero;
+    r.nc = *pv;
+    r.c0 = *pcr;
+    r.a0 = par[0];
+    r.a1 = par[1];
+    return r;
+}
+
+template <bool MULTI>
+__device__ __forceinline__ RowMeta row_final(const Batch &b, const RowRaw &r)
+{
+    const Prob P = prob_of<MULTI>(b, r.t);
+    RowMeta m;
+    m.t = r.t;
+    m.nc = r.nc;
+    m.cs = r.c0 - P.c_off;
+    m.ps = r.a0 - P.a_off;
+    m.pe = r.a1 - P.a_off;
     return m;
+}
+
+// The first chunk of a row: entries ps + lane of row i of A (column -1 past
+// the row) and the row pointers of B at their columns, as loaded (zeros for
+// columns outside [k_lo, k_hi), which then give an empty range).
+struct FirstChunk {
+    int ka;
+    double sa;
+    int r0, r1;
+};
+
+__device__ __forceinline__ void first_a(const Prob &P, const RowMeta &m, int lane, FirstChunk &f)
+{
+    const bool on = m.ps + lane < m.pe;
+    const MLS_G int32_t *pk = on ? gp(P.aci) + m.ps + lane : (const MLS_G int32_t *)k_num_void;
+    const MLS_G double *pa = on ? gp(P.aval) + m.ps + lane : (const MLS_G double *)k_num_zero;
+    f.ka = *pk;
+    f.sa = *pa;
+}
+
+__device__ __forceinline__ void first_b(const Prob &P, FirstChunk &f)
+{
+    const bool in = f.ka >= P.k_lo && f.ka < P.k_hi;
+    const MLS_G int32_t *pb = in ? gp(P.brp) + (f.ka - P.k_lo) : (const MLS_G int32_t *)k_num_zero;
+    f.r0 = pb[0];
+    f.r1 = pb[1];
 }
 
 // FLAT: the (entry, B position) pairs of a staged chunk are flattened, G at a
@@ -336,7 +412,7 @@ constexpr int lds_waves_per_simd(int wg_bytes, int nw)
     return w > 8 ? 8 : (w < 1 ? 1 : w);
 }
 
-template <int G, int CAP, bool PACK, bool FLAT>
+template <int G, int CAP, bool PACK, bool MULTI, bool FLAT>
 struct NumShape {
     static constexpr int W = kWave / G;
     static constexpr int XW = FLAT ? num_flat_words(G) : 0;
@@ -345,14 +421,24 @@ struct NumShape {
     // where LDS already limits a SIMD to 4 waves, registers are free for
     // twice the steps in flight
     static constexpr int DEPTH = OCC <= 4 ? 2 * kNumDepth : kNumDepth;
+    // waves per SIMD the kernel is compiled for: the LDS bound, capped so the
+    // row pipeline's registers fit without spills (a reload from scratch
+    // would wait for every load issued before it): 7 waves (72 VGPRs), 5
+    // (96) for the flattened steps or for batches, 4 (128) for both
+    static constexpr int OCC_CAP = (FLAT && MULTI) ? 4 : ((FLAT || MULTI) ? 5 : 7);
+    static constexpr int OCC_R = OCC < OCC_CAP ? OCC : OCC_CAP;
+    // the next row's first chunk is prefetched where registers allow (at
+    // most 5 waves per SIMD); otherwise a row loads its first chunk when it
+    // starts
+    static constexpr bool PF = !MULTI && OCC_R <= 5;
 };
 
 template <int G, int CAP, bool PACK, bool MULTI, bool FLAT>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
-    MULTI ? (NumShape<G, CAP, PACK, FLAT>::OCC < 5 ? NumShape<G, CAP, PACK, FLAT>::OCC : 5)
-          : NumShape<G, CAP, PACK, FLAT>::OCC))) void k_num_lds(Batch b, Sched sc, int bin)
+    NumShape<G, CAP, PACK, MULTI, FLAT>::OCC_R))) void k_num_lds(Batch b, Sched sc, int bin)
 {
-    constexpr int kNumDepth = NumShape<G, CAP, PACK, FLAT>::DEPTH;
+    constexpr int kNumDepth = NumShape<G, CAP, PACK, MULTI, FLAT>::DEPTH;
+    constexpr bool PF = NumShape<G, CAP, PACK, MULTI, FLAT>::PF;
     static_assert(FLAT || G % kNumDepth == 0, "the staged entries are read kNumDepth at a time");
     constexpr int W = kWave / G;
     constexpr int XW = FLAT ? num_flat_words(G) : 0;
@@ -378,21 +464,46 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
     TaskIter it = task_iter(ntasks, NW);
-    // Rows are software-pipelined: the next row's perm entry is loaded when a
-    // row starts and its metadata (size, row pointers) in the middle of the
-    // row, so a row starts with its dependent index loads already done.
+    // Rows of a slot overlap: with PF three are in flight (the row after next
+    // has its perm entry loading; the next row its metadata, then its first
+    // chunk: A entries during this row's insert and steps, B row pointers
+    // after them), so a row starts with all of its dependent index loads
+    // done. Without PF (fewer registers), the next row's perm entry loads
+    // from the start of a row and its metadata from the middle.
     int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-    int g_cur = -1;
-    if (task >= 0 && task * W + slot < n_bin) g_cur = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
+    const bool h_cur = task >= 0 && task * W + slot < n_bin;
+    const int g_raw = bin_row_issue(sc.perm, sc.err, b.na, start + task * W + slot, h_cur);
+    int task_n = -1, g_n = -1;
+    bool h_n = false;
+    if constexpr (PF) {
+        task_n = task >= 0 ? next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it) : -1;
+        h_n = task_n >= 0 && task_n * W + slot < n_bin;
+        g_n = bin_row_issue(sc.perm, sc.err, b.na, start + task_n * W + slot, h_n);
+    }
     ProbCache pc;
-    RowMeta m = row_meta<MULTI>(b, sc, g_cur >= 0, g_cur, pc);
+    RowRaw mr = row_issue<MULTI>(b, sc, bin_row_checked(sc.err, b.na, g_raw, h_cur), pc);
+    FirstChunk f;
+    if constexpr (PF) {
+        const RowMeta m0 = row_final<MULTI>(b, mr);
+        const Prob P0 = prob_of<MULTI>(b, m0.t);
+        first_a(P0, m0, lane, f);
+        first_b(P0, f);
+        asm volatile("" ::"v"(f.ka), "v"(f.sa), "v"(f.r0), "v"(f.r1), "v"(g_n));
+    }
+    // the loop starts with no load of the prologue pending: the wait counts
+    // at the top of the loop are computed over both ways into it, and a load
+    // pending from the prologue would make the first use there also wait
+    // for the loads the previous row issued last
+    asm volatile("" ::"v"(mr.nc), "v"(mr.c0), "v"(mr.a0), "v"(mr.a1));
     while (task >= 0) {
-        const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
-                            ? bin_row(sc.perm, sc.err, b.na, start + task_n * W + slot) : -1;
-        const bool act_n = g_n >= 0;
+        // PF: the row after next; else the next row
+        const int task_x = (!PF || task_n >= 0) ? next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it) : -1;
+        const bool h_x = task_x >= 0 && task_x * W + slot < n_bin;
+        const int g_x = bin_row_issue(sc.perm, sc.err, b.na, start + task_x * W + slot, h_x);
+        RowRaw mr_n;
+        if constexpr (PF) mr_n = row_issue<MULTI>(b, sc, bin_row_checked(sc.err, b.na, g_n, h_n), pc);
 
-        const bool active = m.active;
+        const RowMeta m = row_final<MULTI>(b, mr);
         const Prob P = prob_of<MULTI>(b, m.t);
         const int nc = m.nc;
         int logcap = ilog2_ceil(2 * nc);
@@ -410,31 +521,52 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
         const int b_off = P.b_off, k_lo = P.k_lo, k_hi = P.k_hi;
         const bool accumulate = P.accumulate != 0;
         const int cs = m.cs, ps = m.ps, pe = m.pe;
-        // the first chunk of row i of A is loaded before C's columns are hashed
-        int ka = -1;
-        double sa = 0.0;
-        if (ps + lane < pe) { ka = aci[ps + lane]; sa = aval[ps + lane]; }
+        // the first chunk of row i of A: loaded during the previous row (PF),
+        // else its entries now and its B row pointers after the insert
+        if constexpr (!PF) first_a(P, m, lane, f);
         // a step over a part of B's rows skips the rows (of one chunk) with no
         // entry in it: most rows of A reach only a few parts
         bool skip = false;
         if (P.ranged) {
-            const unsigned long long bal = __ballot(ka >= k_lo && ka < k_hi);
+            // (the empty asm keeps the test, and the wait for the entries,
+            // inside this branch)
+            int kk = f.ka;
+            asm volatile("" : "+v"(kk));
+            const unsigned long long bal = __ballot(kk >= k_lo && kk < k_hi);
             const unsigned long long gm = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (slot * G);
-            skip = active && pe - ps <= G && (bal & gm) == 0ull;
+            skip = pe - ps <= G && (bal & gm) == 0ull;
         }
         nwave_sync();
         if (!skip) insert_row<G>(tab, acc, logcap, cci, cval, cs, nc, lane, accumulate);
-        m = row_meta<MULTI>(b, sc, act_n, g_n, pc);
         nwave_sync();
+        if constexpr (!PF) {
+            mr_n = row_issue<MULTI>(b, sc, bin_row_checked(sc.err, b.na, g_x, h_x), pc);
+            first_b(P, f);
+        }
+        int ka = f.ka;
+        double sa = f.sa;
+        int r0 = f.r0, r1 = f.r1;
+        // PF: the next row's first A entries load during this row's steps
+        RowMeta mn{};
+        Prob Pn{};
+        if constexpr (PF) {
+            mn = row_final<MULTI>(b, mr_n);
+            Pn = prob_of<MULTI>(b, mn.t);
+            first_a(Pn, mn, lane, f);
+        }
         bool bad = false;
         const int pe_w = skip ? ps : pe;
         for (int pc = ps; pc < pe_w; pc += G) {
-            // stage the chunk: (q0, q1, a) of entry pc + lane
-            int sq0 = 0, sq1 = 0;
-            if (ka >= k_lo && ka < k_hi) {
-                sq0 = brp[ka - k_lo] - b_off;
-                sq1 = brp[ka - k_lo + 1] - b_off;
+            // stage the chunk: (q0, q1, a) of entry pc + lane; the B row
+            // pointers of a later chunk are loaded here, from the entries of A
+            // loaded during the previous chunk
+            if (pc != ps) {
+                const bool in = ka >= k_lo && ka < k_hi;
+                const MLS_G int32_t *pb = in ? brp + (ka - k_lo) : (const MLS_G int32_t *)k_num_zero;
+                r0 = pb[0];
+                r1 = pb[1];
             }
+            const int sq0 = r0 - b_off, sq1 = r1 - b_off;
             par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
             int total = 0;
             if constexpr (FLAT) {
@@ -569,13 +701,27 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
             }
             nwave_sync();
         }
+        // the next row's metadata is taken before this row's stores are
+        // issued (a wait for it at the next row's start would also wait for
+        // the stores: the counter covers both)
+        asm volatile("" ::"v"(mr_n.nc), "v"(mr_n.c0), "v"(mr_n.a0), "v"(mr_n.a1));
+        // PF: the next row's B row pointers (its A entries arrived during the steps)
+        if constexpr (PF) first_b(Pn, f);
         if (bad) atomicOr(sc.err, kErrStructure);
-        if (active && !skip)
+        if (!skip)
             for (int e = lane; e < nc; e += G) cval[cs + e] = acc[e];
-        else if (active && !accumulate)
+        else if (!accumulate)
             for (int e = lane; e < nc; e += G) cval[cs + e] = 0.0;
         nwave_sync();
-        task = task_n;
+        if constexpr (PF) {
+            task = task_n;
+            task_n = task_x;
+            g_n = g_x;
+            h_n = h_x;
+        } else {
+            task = task_x;
+        }
+        mr = mr_n;
     }
 }
 
