@@ -263,6 +263,30 @@ __device__ __forceinline__ int bin_row(const int32_t *perm, uint32_t *err, int n
     return g;
 }
 
+// Constant words read in place of an entry a lane does not need, so that a
+// load needs no branch around it (a branch would make the wave wait for the
+// load where the branches join): all ones (a column or row -1) and zeros.
+static __device__ __attribute__((aligned(16))) int32_t k_ones4[4] = {-1, -1, -1, -1};
+static __device__ __attribute__((aligned(16))) int32_t k_zeros4[4] = {0, 0, 0, 0};
+
+// Pipelined form of bin_row: the perm load is only issued (a lane that wants
+// no row reads -1), and bin_row_checked validates the value where it is first
+// used, a row or more later. A position outside the batch never comes from
+// consistent bins and is flagged at once.
+__device__ __forceinline__ int bin_row_issue(const int32_t *perm, uint32_t *err, int na, int pos, bool want)
+{
+    const bool ok = want && (unsigned)pos < (unsigned)na;
+    if (want && !ok) atomicOr(err, kErrTable);
+    return *(ok ? gp(perm) + pos : (const MLS_G int32_t *)k_ones4);
+}
+
+__device__ __forceinline__ int bin_row_checked(uint32_t *err, int na, int g, bool want)
+{
+    if (!want) return -1;
+    if ((unsigned)g >= (unsigned)na) { atomicOr(err, kErrTable); return -1; }
+    return g;
+}
+
 // Bin start = exclusive prefix of the bin counts.
 __device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
 {

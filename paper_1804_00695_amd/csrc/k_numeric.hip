@@ -307,26 +307,6 @@ __device__ __forceinline__ Prob prob_of(const Batch &b, int t)
 // reads a constant word instead), so its first use can sit a row or more
 // behind it: a use inside a branch would make the wave wait at the branch.
 
-// zero words: the target of such loads for row pointers and values
-__device__ __attribute__((aligned(16))) int32_t k_num_zero[4] = {0, 0, 0, 0};
-
-// Row at position pos of the bin (when want): the perm load is only issued;
-// bin_row_checked validates the value where it is first used. A position
-// outside the batch never comes from consistent bins and is flagged.
-__device__ __forceinline__ int bin_row_issue(const int32_t *perm, uint32_t *err, int na, int pos, bool want)
-{
-    const bool ok = want && (unsigned)pos < (unsigned)na;
-    if (want && !ok) atomicOr(err, kErrTable);
-    return *(ok ? gp(perm) + pos : (const MLS_G int32_t *)k_num_void);
-}
-
-__device__ __forceinline__ int bin_row_checked(uint32_t *err, int na, int g, bool want)
-{
-    if (!want) return -1;
-    if ((unsigned)g >= (unsigned)na) { atomicOr(err, kErrTable); return -1; }
-    return g;
-}
-
 // A row's metadata as loaded: output size and row pointers before their
 // offsets are subtracted (row_final), product t for a batch. A slot with no
 // row reads zeros: no outputs and an empty range of A, so every step of the
@@ -346,7 +326,7 @@ __device__ __forceinline__ RowRaw row_issue(const Batch &b, const Sched &sc, int
         i = g - pc.lo;
     }
     const Prob P = prob_of<MULTI>(b, r.t);
-    const MLS_G int32_t *zero = (const MLS_G int32_t *)k_num_zero;
+    const MLS_G int32_t *zero = (const MLS_G int32_t *)k_zeros4;
     const MLS_G int32_t *pv = on ? gp(sc.val) + g : zero;
     const MLS_G int32_t *pcr = on ? gp(P.crp) + i : zero;
     const MLS_G int32_t *par = on ? gp(P.arp) + i : zero;
@@ -383,7 +363,7 @@ __device__ __forceinline__ void first_a(const Prob &P, const RowMeta &m, int lan
 {
     const bool on = m.ps + lane < m.pe;
     const MLS_G int32_t *pk = on ? gp(P.aci) + m.ps + lane : (const MLS_G int32_t *)k_num_void;
-    const MLS_G double *pa = on ? gp(P.aval) + m.ps + lane : (const MLS_G double *)k_num_zero;
+    const MLS_G double *pa = on ? gp(P.aval) + m.ps + lane : (const MLS_G double *)k_zeros4;
     f.ka = *pk;
     f.sa = *pa;
 }
@@ -391,7 +371,7 @@ __device__ __forceinline__ void first_a(const Prob &P, const RowMeta &m, int lan
 __device__ __forceinline__ void first_b(const Prob &P, FirstChunk &f)
 {
     const bool in = f.ka >= P.k_lo && f.ka < P.k_hi;
-    const MLS_G int32_t *pb = in ? gp(P.brp) + (f.ka - P.k_lo) : (const MLS_G int32_t *)k_num_zero;
+    const MLS_G int32_t *pb = in ? gp(P.brp) + (f.ka - P.k_lo) : (const MLS_G int32_t *)k_zeros4;
     f.r0 = pb[0];
     f.r1 = pb[1];
 }
@@ -562,7 +542,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
             // loaded during the previous chunk
             if (pc != ps) {
                 const bool in = ka >= k_lo && ka < k_hi;
-                const MLS_G int32_t *pb = in ? brp + (ka - k_lo) : (const MLS_G int32_t *)k_num_zero;
+                const MLS_G int32_t *pb = in ? brp + (ka - k_lo) : (const MLS_G int32_t *)k_zeros4;
                 r0 = pb[0];
                 r1 = pb[1];
             }

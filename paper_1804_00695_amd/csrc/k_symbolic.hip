@@ -59,28 +59,70 @@ __device__ __forceinline__ void set_insert_at(uint32_t *key, uint32_t *msk, int 
 
 // Where a row of the bin lives: product t, local row i, its table size
 // bound and its A entry range [ps, pe) (local); g < 0 for no row.
+// Where a row of the bin lives: row g (-1: none), product t, local row i,
+// output bound or size (size) and its A entry range [ps, pe). The loads are
+// issued by sym_issue without a branch around them (a slot without a row
+// reads zeros) and the offsets applied by sym_final, a row later.
 struct SymRow {
     int g, t, i, size, ps, pe;
 };
 
-__device__ __forceinline__ SymRow sym_row(const Batch &b, const Sched &sc, int g, ProbCache &pc)
+__device__ __forceinline__ SymRow sym_issue(const Batch &b, const Sched &sc, int g, ProbCache &pc)
 {
     SymRow m{g, 0, 0, 0, 0, 0};
-    if (g < 0) return m;
-    m.i = g;
-    if (b.nprob > 1) {
+    const bool on = g >= 0;
+    m.i = on ? g : 0;
+    if (b.nprob > 1 && on) {
         m.t = find_prob_cached(b.abase, b.nprob, g, pc);
         m.i = g - pc.lo;
     }
     const Prob P = get_prob(b, m.t);
-    m.size = gp(sc.val)[g];
-    m.ps = gp(P.arp)[m.i] - P.a_off;
-    m.pe = gp(P.arp)[m.i + 1] - P.a_off;
+    const MLS_G int32_t *zero = (const MLS_G int32_t *)k_zeros4;
+    const MLS_G int32_t *pv = on ? gp(sc.val) + g : zero;
+    const MLS_G int32_t *pa = on ? gp(P.arp) + m.i : zero;
+    m.size = *pv;
+    m.ps = pa[0];
+    m.pe = pa[1];
     return m;
 }
 
+__device__ __forceinline__ SymRow sym_final(const Batch &b, const SymRow &r)
+{
+    SymRow m = r;
+    const int a_off = get_prob(b, r.t).a_off;
+    m.ps = r.ps - a_off;
+    m.pe = r.pe - a_off;
+    return m;
+}
+
+// The B row of entry ps + lane of a row of A (its first chunk), located in
+// advance: the column (-1 past the row), then the word offset and count of
+// its compressed row as loaded (zeros for a column outside [k_lo, k_hi): no
+// words).
+struct SymFirst {
+    int k, q0, nw;
+};
+
+__device__ __forceinline__ void sym_first_a(const Batch &b, const SymRow &m, int lane, SymFirst &f)
+{
+    const bool on = m.ps + lane < m.pe;
+    const MLS_G int32_t *pk = on ? gp(get_prob(b, m.t).aci) + m.ps + lane : (const MLS_G int32_t *)k_ones4;
+    f.k = *pk;
+}
+
+__device__ __forceinline__ void sym_first_b(const Batch &b, const SymRow &m, SymFirst &f)
+{
+    const Prob P = get_prob(b, m.t);
+    const bool in = f.k >= P.k_lo && f.k < P.k_hi;
+    const int kl = in ? f.k - P.k_lo : 0;
+    const MLS_G int32_t *zero = (const MLS_G int32_t *)k_zeros4;
+    f.q0 = *(in ? gp(P.brp) + kl : zero);
+    f.nw = *(in ? gp(P.bwc) + kl : zero);
+}
+
 // Waves per SIMD that the count kernel's LDS leaves resident (160 KB per CU,
-// 4 SIMDs), at most 6 (registers for the batched inserts); the kernel is
+// 4 SIMDs), at most 6 for 64 lanes per row and 5 otherwise (registers for the
+// batched inserts and the row pipeline, without spills); the kernel is
 // compiled to fit that many.
 template <int G, int CAP>
 constexpr int sym_count_waves()
@@ -89,7 +131,8 @@ constexpr int sym_count_waves()
     constexpr int NW = nw_for(CAP * 8, W);
     constexpr int wgs = 163840 / (NW * W * CAP * 8);
     constexpr int w = wgs * NW / 4;
-    return w > 6 ? 6 : (w < 1 ? 1 : w);
+    constexpr int cap = G == 64 ? 6 : 5;
+    return w > cap ? cap : (w < 1 ? 1 : w);
 }
 
 template <int G, int CAP, bool FILL>
@@ -124,18 +167,34 @@ void k_sym_lds(Batch b, Sched sc, int bin)
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
     TaskIter it = task_iter(ntasks, NW);
-    // rows are software-pipelined: the next row's perm entry is loaded when a
-    // row starts, its size and row pointers once the row's words are inserted
+    // Rows are software-pipelined, three of a slot in flight: the row after
+    // next has its perm entry loading, the next row its size and row pointers,
+    // then the B rows of its first chunk (the entries of A once this row's
+    // words are inserted, the word offsets and counts after its count), so a
+    // row starts with its dependent index loads done.
     int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-    int g_first = -1;
-    if (task >= 0 && task * W + slot < n_bin) g_first = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
+    const bool h_cur = task >= 0 && task * W + slot < n_bin;
+    const int g_raw = bin_row_issue(sc.perm, sc.err, b.na, start + task * W + slot, h_cur);
+    int task_n = task >= 0 ? next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it) : -1;
+    bool h_n = task_n >= 0 && task_n * W + slot < n_bin;
+    int g_n = bin_row_issue(sc.perm, sc.err, b.na, start + task_n * W + slot, h_n);
     ProbCache pc;
-    SymRow m = sym_row(b, sc, g_first, pc);
-    int pre_q0 = 0, pre_nw = -1;   // the current row's first-chunk B row, when located in advance
+    SymRow mr = sym_issue(b, sc, bin_row_checked(sc.err, b.na, g_raw, h_cur), pc);
+    SymFirst f;
+    {
+        const SymRow m0 = sym_final(b, mr);
+        sym_first_a(b, m0, lane, f);
+        sym_first_b(b, m0, f);
+    }
+    // no prologue load is left pending into the loop (the wait counts at its
+    // top are computed over both ways into it)
+    asm volatile("" ::"v"(f.q0), "v"(f.nw), "v"(g_n), "v"(mr.size), "v"(mr.ps), "v"(mr.pe));
     while (task >= 0) {
-        const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
-                            ? bin_row(sc.perm, sc.err, b.na, start + task_n * W + slot) : -1;
+        const int task_x = task_n >= 0 ? next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it) : -1;
+        const bool h_x = task_x >= 0 && task_x * W + slot < n_bin;
+        const int g_x = bin_row_issue(sc.perm, sc.err, b.na, start + task_x * W + slot, h_x);
+        const SymRow mr_n = sym_issue(b, sc, bin_row_checked(sc.err, b.na, g_n, h_n), pc);
+        const SymRow m = sym_final(b, mr);
         const bool active = m.g >= 0;
         const int g = active ? m.g : 0;
         const int t = m.t;
@@ -166,9 +225,9 @@ void k_sym_lds(Batch b, Sched sc, int bin)
             const int ps = m.ps, pe = m.pe;
             for (int p = ps + lane; p < pe; p += G) {
                 int q0, nw;
-                if (p == ps + lane && pre_nw >= 0) {   // first chunk: B row located during the previous row
-                    q0 = pre_q0;
-                    nw = pre_nw;
+                if (p == ps + lane) {   // first chunk: B row located during the previous row
+                    q0 = f.q0 - b_off;
+                    nw = f.nw;
                 } else {
                     const int k = aci[p];
                     if (k < k_lo || k >= k_hi) continue;
@@ -214,13 +273,12 @@ void k_sym_lds(Batch b, Sched sc, int bin)
                 }
             }
         }
-        m = sym_row(b, sc, g_n, pc);
         wave_sync();
-        // locate the next row's first chunk of B rows while this row is finished:
-        // the entry of A, then the B row's word offset and count
-        pre_nw = -1;
-        int pre_k = -1;
-        if (m.g >= 0 && m.ps + lane < m.pe) pre_k = gp(get_prob(b, m.t).aci)[m.ps + lane];
+        // locate the next row's first chunk of B rows while this row is
+        // finished: the entries of A now, the B rows' word offsets and counts
+        // once they arrive
+        const SymRow mn = sym_final(b, mr_n);
+        sym_first_a(b, mn, lane, f);
         if (!FILL) {
             // one pass over the table: popcount of the union, and the occupied
             // (set, mask) words compacted in slot order into the row's scratch
@@ -265,25 +323,13 @@ void k_sym_lds(Batch b, Sched sc, int bin)
                 base += tot;
             }
             c = group_sum<G>(c);
-            if (pre_k >= 0) {
-                const Prob Pn = get_prob(b, m.t);
-                if (pre_k >= Pn.k_lo && pre_k < Pn.k_hi) {
-                    pre_q0 = gp(Pn.brp)[pre_k - Pn.k_lo] - Pn.b_off;
-                    pre_nw = gp(Pn.bwc)[pre_k - Pn.k_lo];
-                }
-            }
+            sym_first_b(b, mn, f);
             if (active && lane == 0) {
                 val[g] = c;
                 if (sc.scr) gpw(sc.scnt)[g] = base <= kScratchWords ? base : -1;
             }
         } else {
-            if (pre_k >= 0) {
-                const Prob Pn = get_prob(b, m.t);
-                if (pre_k >= Pn.k_lo && pre_k < Pn.k_hi) {
-                    pre_q0 = gp(Pn.brp)[pre_k - Pn.k_lo] - Pn.b_off;
-                    pre_nw = gp(Pn.bwc)[pre_k - Pn.k_lo];
-                }
-            }
+            sym_first_b(b, mn, f);
             for (int h = lane; h < cap; h += G) {
                 uint32_t k = key[h];
                 if (k != kEmptyKey) {
@@ -339,6 +385,10 @@ void k_sym_lds(Batch b, Sched sc, int bin)
         }
         wave_sync();
         task = task_n;
+        task_n = task_x;
+        g_n = g_x;
+        h_n = h_x;
+        mr = mr_n;
     }
 }
 
