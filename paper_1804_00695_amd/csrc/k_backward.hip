@@ -132,18 +132,47 @@ constexpr int kBwdInsDepth = 4;
 
 struct BwdMeta {
     int nw, ws0, ps, pe;
-    bool active;
 };
 
-__device__ __forceinline__ BwdMeta bwd_meta(const Prob &P, const Sched &sc, int g)
+// The loads of a row's metadata (size of W_i, row pointers of W and A),
+// issued without a branch around them (a slot without a row reads zeros: no
+// entries) so that their first use can sit a row later.
+__device__ __forceinline__ BwdMeta bwd_meta_issue(const Prob &P, const Sched &sc, int g)
 {
-    BwdMeta m{0, 0, 0, 0, g >= 0};
-    if (g < 0) return m;
-    m.nw = gp(sc.val)[g];
-    m.ws0 = gp(P.crp)[g];
-    m.ps = gp(P.arp)[g];
-    m.pe = gp(P.arp)[g + 1];
+    const bool on = g >= 0;
+    const MLS_G int32_t *zero = (const MLS_G int32_t *)k_zeros4;
+    const MLS_G int32_t *pv = on ? gp(sc.val) + g : zero;
+    const MLS_G int32_t *pc = on ? gp(P.crp) + g : zero;
+    const MLS_G int32_t *pa = on ? gp(P.arp) + g : zero;
+    BwdMeta m;
+    m.nw = *pv;
+    m.ws0 = *pc;
+    m.ps = pa[0];
+    m.pe = pa[1];
     return m;
+}
+
+// A row's first chunk, located in advance: entries ps + lane of A_i (column
+// -1 and value 0 past the row), then their rows' bounds in B (zeros past the
+// row: no pairs).
+struct BwdFirst {
+    int ka;
+    double sa;
+    int q0, q1;
+};
+
+__device__ __forceinline__ void bwd_first_a(const Prob &P, const BwdMeta &m, int lane, BwdFirst &f)
+{
+    const bool on = m.ps + lane < m.pe;
+    f.ka = *(on ? gp(P.aci) + m.ps + lane : (const MLS_G int32_t *)k_ones4);
+    f.sa = *(on ? gp(P.aval) + m.ps + lane : (const MLS_G double *)k_zeros4);
+}
+
+__device__ __forceinline__ void bwd_first_b(const Prob &P, BwdFirst &f)
+{
+    const MLS_G int32_t *pb = f.ka >= 0 ? gp(P.brp) + f.ka : (const MLS_G int32_t *)k_zeros4;
+    f.q0 = pb[0];
+    f.q1 = pb[1];
 }
 
 template <int G, int CAP>
@@ -183,43 +212,55 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
     const int start = bin_start(sc.bin_count, bin);
     const int ntasks = (n_bin + W - 1) / W;
     TaskIter it = task_iter(ntasks, NW);
+    // Three rows of a slot are in flight: the row after next has its perm
+    // entry loading, the next row its metadata, then its first chunk (entries
+    // of A_i while this row's W_i is hashed, their B row bounds after this
+    // row's pairs), so a row starts with its dependent index loads done.
     int task = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-    int g_cur = -1;
-    if (task >= 0 && task * W + slot < n_bin) g_cur = bin_row(sc.perm, sc.err, b.na, start + task * W + slot);
-    BwdMeta m = bwd_meta(P, sc, g_cur);
+    const bool h_cur = task >= 0 && task * W + slot < n_bin;
+    const int g_raw = bin_row_issue(sc.perm, sc.err, b.na, start + task * W + slot, h_cur);
+    int task_n = task >= 0 ? next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it) : -1;
+    bool h_n = task_n >= 0 && task_n * W + slot < n_bin;
+    int g_n = bin_row_issue(sc.perm, sc.err, b.na, start + task_n * W + slot, h_n);
+    BwdMeta m = bwd_meta_issue(P, sc, bin_row_checked(sc.err, b.na, g_raw, h_cur));
+    BwdFirst f;
+    bwd_first_a(P, m, lane, f);
+    bwd_first_b(P, f);
+    // no prologue load is left pending into the loop (the wait counts at its
+    // top are computed over both ways into it)
+    asm volatile("" ::"v"(f.q0), "v"(f.q1), "v"(f.sa), "v"(g_n), "v"(m.nw), "v"(m.ws0), "v"(m.ps), "v"(m.pe));
     while (task >= 0) {
-        const int task_n = next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it);
-        const int g_n = (task_n >= 0 && task_n * W + slot < n_bin)
-                            ? bin_row(sc.perm, sc.err, b.na, start + task_n * W + slot) : -1;
-        const bool active = m.active;
+        const int task_x = task_n >= 0 ? next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it) : -1;
+        const bool h_x = task_x >= 0 && task_x * W + slot < n_bin;
+        const int g_x = bin_row_issue(sc.perm, sc.err, b.na, start + task_x * W + slot, h_x);
+        const BwdMeta mn = bwd_meta_issue(P, sc, bin_row_checked(sc.err, b.na, g_n, h_n));
         const int nw = m.nw, ws0 = m.ws0, ps = m.ps, pe = m.pe;
         int logcap = ilog2_ceil(2 * nw);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
         for (int h = lane; h < cap; h += G) key[h] = -1;
-        // the first chunk of A_i is in flight while W_i is hashed
-        int ka = -1;
-        double sa = 0.0;
-        if (active && ps + lane < pe) { ka = aci[ps + lane]; sa = aval[ps + lane]; }
+        // this row's first chunk was located during the previous row
+        int ka = f.ka;
+        double sa = f.sa;
+        int fq0 = f.q0, fq1 = f.q1;
         bwd_sync();
-        if (active) {
-            for (int e0 = lane; e0 < nw; e0 += G * kBwdInsDepth) {
-                int jv[kBwdInsDepth];
-                double wj[kBwdInsDepth];
+        for (int e0 = lane; e0 < nw; e0 += G * kBwdInsDepth) {
+            int jv[kBwdInsDepth];
+            double wj[kBwdInsDepth];
 #pragma unroll
-                for (int u = 0; u < kBwdInsDepth; ++u) {
-                    const int e = e0 + u * G;
-                    jv[u] = -1;
-                    wj[u] = 0.0;
-                    if (e < nw) { jv[u] = wci[ws0 + e]; wj[u] = wval[ws0 + e]; }
-                }
-#pragma unroll
-                for (int u = 0; u < kBwdInsDepth; ++u)
-                    if (jv[u] >= 0) w_insert(key, wv, logcap, jv[u], wj[u]);
+            for (int u = 0; u < kBwdInsDepth; ++u) {
+                const int e = e0 + u * G;
+                jv[u] = -1;
+                wj[u] = 0.0;
+                if (e < nw) { jv[u] = wci[ws0 + e]; wj[u] = wval[ws0 + e]; }
             }
+#pragma unroll
+            for (int u = 0; u < kBwdInsDepth; ++u)
+                if (jv[u] >= 0) w_insert(key, wv, logcap, jv[u], wj[u]);
         }
-        m = bwd_meta(P, sc, g_n);   // the next row's metadata, in flight during this row
         bwd_sync();
+        // the next row's first entries of A load during this row's pairs
+        bwd_first_a(P, mn, lane, f);
         bool bad = false;
         // the chunk loop runs to the wave's longest row, so that the group
         // scans (cross-lane shuffles) run with every lane present
@@ -229,7 +270,10 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
             const int pc = ps + c * G;
             int q0 = 0, np = 0;
             const double a = sa;
-            if (pc + lane < pe) {
+            if (c == 0) {
+                q0 = fq0;
+                np = fq1 > fq0 ? fq1 - fq0 : 0;
+            } else if (pc + lane < pe) {
                 q0 = brp[ka];
                 const int q1 = brp[ka + 1];
                 np = q1 > q0 ? q1 - q0 : 0;
@@ -257,6 +301,13 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
                     pofv[x] = v.x; pofv[x + 1] = v.y; pofv[x + 2] = v.z; pofv[x + 3] = v.w;
                 }
             }
+            // the dB adds of a batch are issued after the next batch's loads:
+            // the wait for those loads then does not include them (the
+            // counter covers loads and atomics in issue order)
+            int dq[kBwdUnroll];
+            double dv[kBwdUnroll];
+#pragma unroll
+            for (int d = 0; d < kBwdUnroll; ++d) { dq[d] = -1; dv[d] = 0.0; }
             for (int base = 0; base < total; base += G * kBwdUnroll) {
                 int qv[kBwdUnroll], ev[kBwdUnroll], jv[kBwdUnroll];
                 double bv[kBwdUnroll];
@@ -293,6 +344,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
                     bv[d] = *pv;
                 }
                 __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int d = 0; d < kBwdUnroll; ++d)
+                    if (dq[d] >= 0) atomicAdd(dB + dq[d], dv[d]);
                 int sl[kBwdUnroll];
                 double w[kBwdUnroll];
                 w_lookup_n<kBwdUnroll>(key, wv, logcap, jv, sl, w);
@@ -301,18 +355,28 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
 #pragma unroll
                 for (int d = 0; d < kBwdUnroll; ++d) {
                     if (sl[d] == -1) bad = true;
+                    dq[d] = -1;
                     if (sl[d] < 0) continue;
                     if (dA) atomicAdd(da + ev[d], w[d] * bv[d]);
-                    if (dB) atomicAdd(dB + qv[d], pa[ev[d]] * w[d]);
+                    if (dB) { dq[d] = qv[d]; dv[d] = pa[ev[d]] * w[d]; }
                 }
             }
+#pragma unroll
+            for (int d = 0; d < kBwdUnroll; ++d)
+                if (dq[d] >= 0) atomicAdd(dB + dq[d], dv[d]);
             bwd_sync();
             if (dA && pc + lane < pe) gdA[pc + lane] = da[lane];
             bwd_sync();
         }
+        // the next row's B row bounds (its entries of A arrived during the pairs)
+        bwd_first_b(P, f);
         if (bad) atomicOr(sc.err, kErrStructure);
         bwd_sync();
         task = task_n;
+        task_n = task_x;
+        g_n = g_x;
+        h_n = h_x;
+        m = mn;
     }
 }
 
