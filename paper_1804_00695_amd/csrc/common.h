@@ -302,8 +302,11 @@ __device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
 // by b div S, with S the number of waves the grid places on the XCD. While
 // every wave is busy, the rows in flight on an XCD therefore form a narrow
 // window of about S consecutive tasks (neighbouring rows share most of their
-// rows of B, and a narrow window keeps that shared working set in the L2),
-// and workgroups that become resident late, or never, leave no tasks behind.
+// rows of B, and a narrow window keeps that shared working set in the L2).
+// A wave's first block is the one of its own index on the XCD (the grid is
+// sized to be resident at once), so a launch does not start with every wave
+// queued on the same counter; only the blocks after the first S are taken
+// from the counter, and a slab that the first blocks cover takes none.
 constexpr int kTaskBlock = 8;
 
 //
@@ -313,7 +316,8 @@ constexpr int kTaskBlock = 8;
 // row index (the degree-ordered rows of a power-law graph), where contiguous
 // slabs leave some XCDs idle while others still work.
 struct TaskIter {
-    int lo, hi, S, cur, left, x, lc;
+    int lo, hi, S, cur, left, x, lc, wid;
+    bool first;
 };
 
 __device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg, int log_chunk = -1)
@@ -339,6 +343,8 @@ __device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg, int 
     if (it.S < 1) it.S = 1;
     it.cur = 0;
     it.left = 0;
+    it.wid = (int)(blockIdx.x / kXcd) * waves_per_wg + (int)(threadIdx.x >> 6);   // in [0, S)
+    it.first = true;
     return it;
 }
 
@@ -363,8 +369,14 @@ __device__ __forceinline__ int next_task_wave(int32_t *cursor, int ntasks, TaskI
             it.left = 0;
         }
         int blk = 0;
-        if ((threadIdx.x & 63) == 0) blk = atomicAdd(cursor + blockIdx.x % kXcd, 1);
-        blk = __builtin_amdgcn_readlane(blk, 0);
+        if (it.first) {
+            blk = it.wid;
+            it.first = false;
+        } else {
+            if ((int64_t)it.lo + (int64_t)it.S * kTaskBlock >= it.hi) return -1;   // no block past the first S
+            if ((threadIdx.x & 63) == 0) blk = atomicAdd(cursor + blockIdx.x % kXcd, 1);
+            blk = __builtin_amdgcn_readlane(blk, 0) + it.S;
+        }
         const int64_t base = (int64_t)it.lo + (int64_t)(blk / it.S) * it.S * kTaskBlock + blk % it.S;
         if (base >= it.hi) return -1;
         it.cur = (int)base;

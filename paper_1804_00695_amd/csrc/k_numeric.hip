@@ -525,7 +525,27 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
         }
         int ka = f.ka;
         double sa = f.sa;
-        int r0 = f.r0, r1 = f.r1;
+        bool bad = false;
+        const int pe_w = skip ? ps : pe;
+        // stage a chunk: (q0, q1, a) of its entry pc + lane, from the B row
+        // pointers as loaded; FLAT: the group's pair offsets and pair count
+        auto stage = [&](int q0r, int q1r, double a) -> int {
+            const int sq0 = q0r - b_off, sq1 = q1r - b_off;
+            par[lane] = make_int4(sq0, sq1, __double2loint(a), __double2hiint(a));
+            int tot = 0;
+            if constexpr (FLAT) {
+                const int np = sq1 > sq0 ? sq1 - sq0 : 0;
+                const int incl = group_scan_incl<G>(np, lane);
+                tot = group_total<G>(np, incl);
+                poff[lane] = incl - np;
+            }
+            return tot;
+        };
+        // the first chunk is staged here from what was loaded during the
+        // previous row (unused when the row has no chunk), the later ones in
+        // the chunk loop: no loaded value reaches a point where the two ways
+        // join, where its wait would also cover the loads issued since
+        int total = stage(f.r0, f.r1, f.sa);
         // PF: the next row's first A entries load during this row's steps
         RowMeta mn{};
         Prob Pn{};
@@ -534,32 +554,24 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(
             Pn = prob_of<MULTI>(b, mn.t);
             first_a(Pn, mn, lane, f);
         }
-        bool bad = false;
-        const int pe_w = skip ? ps : pe;
         for (int pc = ps; pc < pe_w; pc += G) {
-            // stage the chunk: (q0, q1, a) of entry pc + lane; the B row
-            // pointers of a later chunk are loaded here, from the entries of A
-            // loaded during the previous chunk
             if (pc != ps) {
+                // a later chunk: the B row pointers of the entries of A loaded
+                // during the previous chunk
                 const bool in = ka >= k_lo && ka < k_hi;
                 const MLS_G int32_t *pb = in ? brp + (ka - k_lo) : (const MLS_G int32_t *)k_zeros4;
-                r0 = pb[0];
-                r1 = pb[1];
-            }
-            const int sq0 = r0 - b_off, sq1 = r1 - b_off;
-            par[lane] = make_int4(sq0, sq1, __double2loint(sa), __double2hiint(sa));
-            int total = 0;
-            if constexpr (FLAT) {
-                const int np = sq1 > sq0 ? sq1 - sq0 : 0;
-                int incl = group_scan_incl<G>(np, lane);
-                total = group_total<G>(np, incl);
-                poff[lane] = incl - np;
+                total = stage(pb[0], pb[1], sa);
             }
             nwave_sync();
-            // the next chunk's entries of A are in flight during this chunk's steps
-            ka = -1;
-            sa = 0.0;
-            if (pc + G + lane < pe) { ka = aci[pc + G + lane]; sa = aval[pc + G + lane]; }
+            // the next chunk's entries of A are in flight during this chunk's
+            // steps (loaded without a branch: a default written into their
+            // registers before a conditional load would wait for the loads of
+            // the previous chunk, and with them for everything issued since)
+            {
+                const bool on = pc + G + lane < pe;
+                ka = *(on ? aci + pc + G + lane : (const MLS_G int32_t *)k_ones4);
+                sa = *(on ? aval + pc + G + lane : (const MLS_G double *)k_zeros4);
+            }
             const int n = FLAT ? 0 : min(G, pe - pc);
             if constexpr (FLAT) {
                 // the group's pair offsets in registers: a pair's entry is the
