@@ -259,36 +259,43 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
                 if (jv[u] >= 0) w_insert(key, wv, logcap, jv[u], wj[u]);
         }
         bwd_sync();
-        // the next row's first entries of A load during this row's pairs
-        bwd_first_a(P, mn, lane, f);
         bool bad = false;
         // the chunk loop runs to the wave's longest row, so that the group
         // scans (cross-lane shuffles) run with every lane present
         int nch = (pe - ps + G - 1) / G;
         for (int o = 32; o >= 1; o >>= 1) nch = max(nch, __shfl_xor(nch, o, kWave));
-        for (int c = 0; c < nch; ++c) {
-            const int pc = ps + c * G;
-            int q0 = 0, np = 0;
-            const double a = sa;
-            if (c == 0) {
-                q0 = fq0;
-                np = fq1 > fq0 ? fq1 - fq0 : 0;
-            } else if (pc + lane < pe) {
-                q0 = brp[ka];
-                const int q1 = brp[ka + 1];
-                np = q1 > q0 ? q1 - q0 : 0;
-            }
-            // the next chunk's entries of A are in flight during this chunk's pairs
-            ka = -1;
-            sa = 0.0;
-            if (pc + G + lane < pe) { ka = aci[pc + G + lane]; sa = aval[pc + G + lane]; }
-            int incl = group_scan_incl<G>(np, lane);
-            const int total = group_total<G>(np, incl);
+        // stage a chunk: its entries' first B positions, pair offsets, a_ik
+        // and zeroed dA sums; returns the chunk's pair count
+        auto stage = [&](int q0, int q1, double a) -> int {
+            const int np = q1 > q0 ? q1 - q0 : 0;
+            const int incl = group_scan_incl<G>(np, lane);
+            const int tot = group_total<G>(np, incl);
             poff[lane] = incl - np;
-            if (lane == 0) poff[G] = total;
+            if (lane == 0) poff[G] = tot;
             pq[lane] = q0;
             pa[lane] = a;
             da[lane] = 0.0;
+            return tot;
+        };
+        // the first chunk from what was located during the previous row, the
+        // later ones in the loop: no loaded value reaches a point where two
+        // ways join (its wait there would cover every load issued since)
+        int total = stage(fq0, fq1, sa);
+        // the next row's first entries of A load during this row's pairs
+        bwd_first_a(P, mn, lane, f);
+        for (int c = 0; c < nch; ++c) {
+            const int pc = ps + c * G;
+            if (c > 0) {
+                const MLS_G int32_t *pb = pc + lane < pe ? brp + ka : (const MLS_G int32_t *)k_zeros4;
+                total = stage(pb[0], pb[1], sa);
+            }
+            // the next chunk's entries of A are in flight during this chunk's
+            // pairs (no branch: see the numeric kernel's chunk loop)
+            {
+                const bool on = pc + G + lane < pe;
+                ka = *(on ? aci + pc + G + lane : (const MLS_G int32_t *)k_ones4);
+                sa = *(on ? aval + pc + G + lane : (const MLS_G double *)k_zeros4);
+            }
             bwd_sync();
             // groups of at most 16 lanes keep the pair offsets in registers: a
             // pair's entry is the last one whose offset is at most its index
