@@ -307,7 +307,7 @@ __device__ __forceinline__ int bin_start(const int32_t *bin_count, int bin)
 // sized to be resident at once), so a launch does not start with every wave
 // queued on the same counter; only the blocks after the first S are taken
 // from the counter, and a slab that the first blocks cover takes none.
-constexpr int kTaskBlock = 8;
+constexpr int kTaskBlock = 16;
 
 //
 // With log_chunk >= 0 the tasks are instead cut into chunks of 2^log_chunk
