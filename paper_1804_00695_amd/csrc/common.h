@@ -135,6 +135,38 @@ __device__ __forceinline__ int find_prob(const int32_t *base, int nprob, int g)
     return lo;
 }
 
+// find_prob for a g that is the same in every lane of the wave, all lanes
+// active: 64 candidates per step, so one or two dependent loads (up to 4096
+// products) in place of log2(nprob).
+__device__ __forceinline__ int find_prob_wave(const int32_t *base, int nprob, int g)
+{
+    if (nprob > 4096) return find_prob(base, nprob, g);
+    const int lane = (int)(threadIdx.x & 63);
+    const MLS_G int32_t *bs = gp(base);
+    int t = 0;
+    if (nprob > 64) {
+        const int c = lane * 64;
+        const int v = bs[c < nprob ? c : 0];
+        const unsigned long long m = __ballot(c < nprob && v <= g);   // lane 0 always: base[0] = 0
+        t = (63 - __clzll(m)) * 64;
+    }
+    const int c = t + lane;
+    const int v = bs[c < nprob ? c : 0];
+    const unsigned long long m = __ballot(c < nprob && v <= g);
+    return t + (63 - __clzll(m));
+}
+
+// Product of row g when consecutive rows are spread over a wave (g = g_w +
+// lane, g_w uniform): the product of the wave's first row serves every lane
+// whose row lies before that product's end, the others search on their own.
+// Call with every lane of the wave active.
+__device__ __forceinline__ int find_prob_rows(const int32_t *base, int nprob, int g_w, int g)
+{
+    const int t = find_prob_wave(base, nprob, g_w);
+    if (g < gp(base)[t + 1]) return t;
+    return find_prob(base, nprob, g);
+}
+
 // Product lookup with a per-lane memory of the last product found: rows a
 // lane takes in a row usually belong to the same product of a batch, and then
 // two compares replace the binary search.

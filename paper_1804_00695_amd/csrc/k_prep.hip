@@ -82,9 +82,10 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
     bool bad = false, longrow = false, midrow = false;
     const int32_t *ci_row = nullptr;   // entries of this thread's row (long rows)
     int len = 0, ncols = 0;
+    const int32_t *base = which == 0 ? b.abase : b.bbase;
+    const int t_row = b.nprob == 1 ? 0 : find_prob_rows(base, b.nprob, g - lane, g);
     if (g < total) {
-        const int32_t *base = which == 0 ? b.abase : b.bbase;
-        const int t = b.nprob == 1 ? 0 : find_prob(base, b.nprob, g);
+        const int t = t_row;
         const Prob P = get_prob(b, t);
         const int i = g - (b.nprob == 1 ? 0 : gp(base)[t]);
         const MLS_G int32_t *rp = gp(which == 0 ? P.arp : P.brp);
@@ -244,8 +245,9 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
     uint2 *out_row = nullptr;
     int32_t *cnt_ptr = nullptr;
     int len = 0;
+    const int t_row = b.nprob == 1 ? 0 : find_prob_rows(b.bbase, b.nprob, g - (int)(threadIdx.x & 63), g);
     if (g < b.nb) {
-        const int t = b.nprob == 1 ? 0 : find_prob(b.bbase, b.nprob, g);
+        const int t = t_row;
         const Prob P = get_prob(b, t);
         const int k = g - (b.nprob == 1 ? 0 : gp(b.bbase)[t]);
         const int s0 = gp(P.brp)[k] - P.b_off;
@@ -451,6 +453,13 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
     __syncthreads();
     const int g0 = blockIdx.x * kBinRowsPerWG;
     ProbCache pc;
+    if (b.nprob > 1) {
+        // the product of the block's first row, searched once per wave: the
+        // block's rows almost always belong to it
+        pc.t = find_prob_wave(b.abase, b.nprob, g0);
+        pc.lo = gp(b.abase)[pc.t];
+        pc.hi = gp(b.abase)[pc.t + 1];
+    }
     if (mode == kModeNumeric) {   // size = nnz(C_i): one thread per row
         for (int r = threadIdx.x; r < kBinRowsPerWG; r += kWG) {
             const int g = g0 + r;
@@ -743,8 +752,8 @@ __global__ void k_scan_apply(const int32_t *val, int n, const int64_t *tile_off,
 __global__ void k_write_rowptr(Batch b, const int64_t *prefix, int64_t *totals, uint32_t *err)
 {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = b.nprob == 1 ? 0 : find_prob_rows(b.abase, b.nprob, g - (int)(threadIdx.x & 63), g);
     if (g >= b.na) return;
-    int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
     const Prob P = get_prob(b, t);
     int r0 = b.nprob == 1 ? 0 : gp(b.abase)[t];
     int i = g - r0;
