@@ -196,6 +196,33 @@ __device__ __forceinline__ Prob get_prob(const Batch &b, int t)
     return P;
 }
 
+// get_prob for kernels specialised for batches: when every active lane of
+// the wave asks for the same product (the rows of a wave are consecutive, so
+// almost always), the descriptor is read once through the scalar cache
+// (constant address space: the descriptors do not change while a kernel
+// runs) and waits only on the scalar counter; otherwise each lane reads its
+// own, and that wait stays inside its branch.
+typedef const __attribute__((address_space(4))) u32x4 *MLS_K_u32x4p;
+
+__device__ __forceinline__ Prob get_prob_batch(const Batch &b, int t)
+{
+    Prob P;
+    u32x4 *dst = (u32x4 *)&P;
+    const int t0 = __builtin_amdgcn_readfirstlane(t);
+    if (__ballot(t != t0) == 0ull) {
+        const MLS_K_u32x4p src = (MLS_K_u32x4p)(b.probs + t0);
+#pragma unroll
+        for (int w = 0; w < (int)(sizeof(Prob) / 16); ++w) dst[w] = src[w];
+    } else {
+        const MLS_G u32x4 *src = (const MLS_G u32x4 *)(b.probs + t);
+#pragma unroll
+        for (int w = 0; w < (int)(sizeof(Prob) / 16); ++w) dst[w] = src[w];
+#pragma unroll
+        for (int w = 0; w < (int)(sizeof(Prob) / 16); ++w) asm volatile("" ::"v"(dst[w]));
+    }
+    return P;
+}
+
 // Multiplicative (Fibonacci) hashing of a 32-bit key into 2^logcap slots.
 __device__ __forceinline__ uint32_t hslot(uint32_t key, int logcap)
 {
@@ -375,7 +402,9 @@ __device__ __forceinline__ TaskIter task_iter(int ntasks, int waves_per_wg, int 
     if (it.S < 1) it.S = 1;
     it.cur = 0;
     it.left = 0;
-    it.wid = (int)(blockIdx.x / kXcd) * waves_per_wg + (int)(threadIdx.x >> 6);   // in [0, S)
+    // in [0, S); read from the first lane so that the compiler keeps it, and
+    // every task index derived from it, in scalar registers
+    it.wid = (int)(blockIdx.x / kXcd) * waves_per_wg + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     it.first = true;
     return it;
 }
