@@ -59,6 +59,16 @@ __device__ __forceinline__ void set_insert_at(uint32_t *key, uint32_t *msk, int 
 
 // Where a row of the bin lives: product t, local row i, its table size
 // bound and its A entry range [ps, pe) (local); g < 0 for no row.
+// The descriptor of product t: the kernel argument for a single product (the
+// kernels are specialised for it), else read once per wave when the wave's
+// rows share their product.
+template <bool MULTI>
+__device__ __forceinline__ Prob sym_prob(const Batch &b, int t)
+{
+    if (!MULTI) return b.p0;
+    return get_prob_batch(b, t);
+}
+
 // Where a row of the bin lives: row g (-1: none), product t, local row i,
 // output bound or size (size) and its A entry range [ps, pe). The loads are
 // issued by sym_issue without a branch around them (a slot without a row
@@ -67,16 +77,17 @@ struct SymRow {
     int g, t, i, size, ps, pe;
 };
 
+template <bool MULTI>
 __device__ __forceinline__ SymRow sym_issue(const Batch &b, const Sched &sc, int g, ProbCache &pc)
 {
     SymRow m{g, 0, 0, 0, 0, 0};
     const bool on = g >= 0;
     m.i = on ? g : 0;
-    if (b.nprob > 1 && on) {
+    if (MULTI && on) {
         m.t = find_prob_cached(b.abase, b.nprob, g, pc);
         m.i = g - pc.lo;
     }
-    const Prob P = get_prob(b, m.t);
+    const Prob P = sym_prob<MULTI>(b, m.t);
     const MLS_G int32_t *zero = (const MLS_G int32_t *)k_zeros4;
     const MLS_G int32_t *pv = on ? gp(sc.val) + g : zero;
     const MLS_G int32_t *pa = on ? gp(P.arp) + m.i : zero;
@@ -86,10 +97,11 @@ __device__ __forceinline__ SymRow sym_issue(const Batch &b, const Sched &sc, int
     return m;
 }
 
+template <bool MULTI>
 __device__ __forceinline__ SymRow sym_final(const Batch &b, const SymRow &r)
 {
     SymRow m = r;
-    const int a_off = get_prob(b, r.t).a_off;
+    const int a_off = sym_prob<MULTI>(b, r.t).a_off;
     m.ps = r.ps - a_off;
     m.pe = r.pe - a_off;
     return m;
@@ -103,16 +115,18 @@ struct SymFirst {
     int k, q0, nw;
 };
 
+template <bool MULTI>
 __device__ __forceinline__ void sym_first_a(const Batch &b, const SymRow &m, int lane, SymFirst &f)
 {
     const bool on = m.ps + lane < m.pe;
-    const MLS_G int32_t *pk = on ? gp(get_prob(b, m.t).aci) + m.ps + lane : (const MLS_G int32_t *)k_ones4;
+    const MLS_G int32_t *pk = on ? gp(sym_prob<MULTI>(b, m.t).aci) + m.ps + lane : (const MLS_G int32_t *)k_ones4;
     f.k = *pk;
 }
 
+template <bool MULTI>
 __device__ __forceinline__ void sym_first_b(const Batch &b, const SymRow &m, SymFirst &f)
 {
-    const Prob P = get_prob(b, m.t);
+    const Prob P = sym_prob<MULTI>(b, m.t);
     const bool in = f.k >= P.k_lo && f.k < P.k_hi;
     const int kl = in ? f.k - P.k_lo : 0;
     const MLS_G int32_t *zero = (const MLS_G int32_t *)k_zeros4;
@@ -121,22 +135,22 @@ __device__ __forceinline__ void sym_first_b(const Batch &b, const SymRow &m, Sym
 }
 
 // Waves per SIMD that the count kernel's LDS leaves resident (160 KB per CU,
-// 4 SIMDs), at most 6 for 64 lanes per row and 5 otherwise (registers for the
-// batched inserts and the row pipeline, without spills); the kernel is
-// compiled to fit that many.
-template <int G, int CAP>
+// 4 SIMDs), at most 6 for 64 lanes per row and 5 otherwise, one fewer for
+// batches (registers for the batched inserts and the row pipeline, without
+// spills); the kernel is compiled to fit that many.
+template <int G, int CAP, bool MULTI>
 constexpr int sym_count_waves()
 {
     constexpr int W = kWave / G;
     constexpr int NW = nw_for(CAP * 8, W);
     constexpr int wgs = 163840 / (NW * W * CAP * 8);
     constexpr int w = wgs * NW / 4;
-    constexpr int cap = G == 64 ? 6 : 5;
+    constexpr int cap = MULTI ? (G == 64 ? 5 : 4) : (G == 64 ? 6 : 5);
     return w > cap ? cap : (w < 1 ? 1 : w);
 }
 
-template <int G, int CAP, bool FILL>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : sym_count_waves<G, CAP>())))
+template <int G, int CAP, bool FILL, bool MULTI>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(FILL ? 1 : sym_count_waves<G, CAP, MULTI>())))
 void k_sym_lds(Batch b, Sched sc, int bin)
 {
     constexpr int W = kWave / G;
@@ -179,12 +193,12 @@ void k_sym_lds(Batch b, Sched sc, int bin)
     bool h_n = task_n >= 0 && task_n * W + slot < n_bin;
     int g_n = bin_row_issue(sc.perm, sc.err, b.na, start + task_n * W + slot, h_n);
     ProbCache pc;
-    SymRow mr = sym_issue(b, sc, bin_row_checked(sc.err, b.na, g_raw, h_cur), pc);
+    SymRow mr = sym_issue<MULTI>(b, sc, bin_row_checked(sc.err, b.na, g_raw, h_cur), pc);
     SymFirst f;
     {
-        const SymRow m0 = sym_final(b, mr);
-        sym_first_a(b, m0, lane, f);
-        sym_first_b(b, m0, f);
+        const SymRow m0 = sym_final<MULTI>(b, mr);
+        sym_first_a<MULTI>(b, m0, lane, f);
+        sym_first_b<MULTI>(b, m0, f);
     }
     // no prologue load is left pending into the loop (the wait counts at its
     // top are computed over both ways into it)
@@ -193,12 +207,12 @@ void k_sym_lds(Batch b, Sched sc, int bin)
         const int task_x = task_n >= 0 ? next_task_wave(sc.task_cursor + bin * kXcd, ntasks, it) : -1;
         const bool h_x = task_x >= 0 && task_x * W + slot < n_bin;
         const int g_x = bin_row_issue(sc.perm, sc.err, b.na, start + task_x * W + slot, h_x);
-        const SymRow mr_n = sym_issue(b, sc, bin_row_checked(sc.err, b.na, g_n, h_n), pc);
-        const SymRow m = sym_final(b, mr);
+        const SymRow mr_n = sym_issue<MULTI>(b, sc, bin_row_checked(sc.err, b.na, g_n, h_n), pc);
+        const SymRow m = sym_final<MULTI>(b, mr);
         const bool active = m.g >= 0;
         const int g = active ? m.g : 0;
         const int t = m.t;
-        const Prob P = get_prob(b, t);
+        const Prob P = sym_prob<MULTI>(b, t);
         const int i = m.i;
         const int size = m.size;
         int logcap = ilog2_ceil(FILL ? 2 * size : size);
@@ -277,8 +291,8 @@ void k_sym_lds(Batch b, Sched sc, int bin)
         // locate the next row's first chunk of B rows while this row is
         // finished: the entries of A now, the B rows' word offsets and counts
         // once they arrive
-        const SymRow mn = sym_final(b, mr_n);
-        sym_first_a(b, mn, lane, f);
+        const SymRow mn = sym_final<MULTI>(b, mr_n);
+        sym_first_a<MULTI>(b, mn, lane, f);
         if (!FILL) {
             // one pass over the table: popcount of the union, and the occupied
             // (set, mask) words compacted in slot order into the row's scratch
@@ -323,13 +337,13 @@ void k_sym_lds(Batch b, Sched sc, int bin)
                 base += tot;
             }
             c = group_sum<G>(c);
-            sym_first_b(b, mn, f);
+            sym_first_b<MULTI>(b, mn, f);
             if (active && lane == 0) {
                 val[g] = c;
                 if (sc.scr) gpw(sc.scnt)[g] = base <= kScratchWords ? base : -1;
             }
         } else {
-            sym_first_b(b, mn, f);
+            sym_first_b<MULTI>(b, mn, f);
             for (int h = lane; h < cap; h += G) {
                 uint32_t k = key[h];
                 if (k != kEmptyKey) {
@@ -718,7 +732,7 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
             wave_sync();
             if (n > 0) {
                 const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
-                const Prob P = get_prob(b, t);
+                const Prob P = b.nprob == 1 ? b.p0 : get_prob_batch(b, t);
                 const int i = g - (b.nprob == 1 ? 0 : pc.lo);
                 const int cs = gp(P.crp)[i] - P.c_off;
                 const int ce = gp(P.crp)[i + 1] - P.c_off;
@@ -780,11 +794,16 @@ static void launch_sym_class(const Batch &b, const Sched &sc, int bin, hipStream
 {
     constexpr int W = kWave / G;
     constexpr int NW = nw_for(FILL ? CAP * 12 : CAP * 8, W);
-    static int grid = persistent_grid(k_sym_lds<G, CAP, FILL>, NW * kWave);
     static char name[64];
     if (!name[0]) snprintf(name, sizeof(name), "sym_%s_lds_G%d_C%d", FILL ? "fill" : "count", G, CAP);
     ProfScope ps(name, s);
-    hipLaunchKernelGGL((k_sym_lds<G, CAP, FILL>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
+    if (b.nprob > 1) {
+        static int grid = persistent_grid(k_sym_lds<G, CAP, FILL, true>, NW * kWave);
+        hipLaunchKernelGGL((k_sym_lds<G, CAP, FILL, true>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
+    } else {
+        static int grid = persistent_grid(k_sym_lds<G, CAP, FILL, false>, NW * kWave);
+        hipLaunchKernelGGL((k_sym_lds<G, CAP, FILL, false>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin);
+    }
 }
 
 template <bool FILL>
