@@ -223,6 +223,13 @@ __device__ __forceinline__ Prob get_prob_batch(const Batch &b, int t)
     return P;
 }
 
+// get_prob_batch for kernels that serve both (the choice is made at run time).
+__device__ __forceinline__ Prob get_prob_any(const Batch &b, int t)
+{
+    if (b.nprob == 1) return b.p0;
+    return get_prob_batch(b, t);
+}
+
 // Multiplicative (Fibonacci) hashing of a 32-bit key into 2^logcap slots.
 __device__ __forceinline__ uint32_t hslot(uint32_t key, int logcap)
 {

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kWG) void k_validate(Batch b, int which, const int6
     const int t_row = b.nprob == 1 ? 0 : find_prob_rows(base, b.nprob, g - lane, g);
     if (g < total) {
         const int t = t_row;
-        const Prob P = get_prob(b, t);
+        const Prob P = get_prob_any(b, t);
         const int i = g - (b.nprob == 1 ? 0 : gp(base)[t]);
         const MLS_G int32_t *rp = gp(which == 0 ? P.arp : P.brp);
         const int32_t *ci = which == 0 ? P.aci : P.bci;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kWG) void k_compress(Batch b)
     const int t_row = b.nprob == 1 ? 0 : find_prob_rows(b.bbase, b.nprob, g - (int)(threadIdx.x & 63), g);
     if (g < b.nb) {
         const int t = t_row;
-        const Prob P = get_prob(b, t);
+        const Prob P = get_prob_any(b, t);
         const int k = g - (b.nprob == 1 ? 0 : gp(b.bbase)[t]);
         const int s0 = gp(P.brp)[k] - P.b_off;
         len = gp(P.brp)[k + 1] - P.b_off - s0;
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
             const int g = g0 + r;
             if (g >= b.na) break;
             const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
-            const Prob P = get_prob(b, t);
+            const Prob P = get_prob_any(b, t);
             const int i = g - (b.nprob == 1 ? 0 : pc.lo);
             const int nc = gp(P.crp)[i + 1] - gp(P.crp)[i];
             const int c = class_of(mode, nc, force);
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
         const int g = g0 + r;
         if (g >= b.na) break;   // uniform per row group
         const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
-        const Prob P = get_prob(b, t);
+        const Prob P = get_prob_any(b, t);
         const int i = g - (b.nprob == 1 ? 0 : pc.lo);
         // fill pass: rows whose words the count pass kept are expanded, not binned
         const bool from_scratch = mode == kModeFill && sc.scr && gp(sc.scnt)[g] >= 0;
@@ -528,7 +528,7 @@ __global__ __launch_bounds__(kWG) void k_bin(Batch b, int mode, Sched sc, int fo
     for (int x = 0; x < nlong; ++x) {
         const int g = g0 + s_long[x];
         const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
-        const Prob P = get_prob(b, t);
+        const Prob P = get_prob_any(b, t);
         const int i = g - (b.nprob == 1 ? 0 : pc.lo);
         const MLS_G int32_t *__restrict__ aci = gp(P.aci);
         const MLS_G int32_t *__restrict__ brp = gp(P.brp);
@@ -754,7 +754,7 @@ __global__ void k_write_rowptr(Batch b, const int64_t *prefix, int64_t *totals, 
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int t = b.nprob == 1 ? 0 : find_prob_rows(b.abase, b.nprob, g - (int)(threadIdx.x & 63), g);
     if (g >= b.na) return;
-    const Prob P = get_prob(b, t);
+    const Prob P = get_prob_any(b, t);
     int r0 = b.nprob == 1 ? 0 : gp(b.abase)[t];
     int i = g - r0;
     int64_t v = prefix[g + 1] - prefix[r0];

@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kWG) void k_sym_spill(Batch b, Sched sc, int fill, 
         const int g = bin_row(sc.perm, sc.err, b.na, start + r);
         if (g < 0) continue;
         const int t = b.nprob == 1 ? 0 : find_prob(b.abase, b.nprob, g);
-        const Prob P = get_prob(b, t);
+        const Prob P = get_prob_any(b, t);
         const int i = g - (b.nprob == 1 ? 0 : gp(b.abase)[t]);
         const MLS_G int32_t *__restrict__ aci = gp(P.aci);
         const MLS_G int32_t *__restrict__ brp = gp(P.brp);
@@ -603,7 +603,7 @@ __device__ __forceinline__ ExpandRow expand_load(const Batch &b, const Sched &sc
         r.t = find_prob_cached(b.abase, b.nprob, g, pc);
         i = g - pc.lo;
     }
-    const Prob P = get_prob(b, r.t);
+    const Prob P = get_prob_any(b, r.t);
     r.cs = gp(P.crp)[i] - P.c_off;
     r.ce = gp(P.crp)[i + 1] - P.c_off;
     return r;
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(kWG) void k_sym_expand(Batch b, Sched sc)
                 nn = __builtin_amdgcn_readlane(nl, rn);
             }
             const ExpandRow nxt = expand_load(b, sc, rn >= 0 ? base + rn : -1, nn, lane, pc);
-            MLS_G int32_t *__restrict__ cci = gpw(get_prob(b, cur.t).cci);
+            MLS_G int32_t *__restrict__ cci = gpw(get_prob_any(b, cur.t).cci);
             const uint32_t set = cur.w.x;
             // set < 2^26 (columns < 2^31) and a popcount <= 32 share one word:
             // set << 6 | popcount, so one lane read carries both, and
