@@ -732,7 +732,9 @@ __global__ __launch_bounds__(kWG) void k_sym_expand_small(Batch b, Sched sc)
             wave_sync();
             if (n > 0) {
                 const int t = b.nprob == 1 ? 0 : find_prob_cached(b.abase, b.nprob, g, pc);
-                const Prob P = b.nprob == 1 ? b.p0 : get_prob_batch(b, t);
+                // (per-lane read: this loop's LDS waits share the scalar
+                // loads' counter, so a scalar descriptor read costs more here)
+                const Prob P = get_prob(b, t);
                 const int i = g - (b.nprob == 1 ? 0 : pc.lo);
                 const int cs = gp(P.crp)[i] - P.c_off;
                 const int ce = gp(P.crp)[i + 1] - P.c_off;
