@@ -113,6 +113,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE))) void
     // the work of a row of L drifts with its degree rank: chunks of 32 tasks
     // dealt to the XCDs round-robin keep the XCDs evenly loaded
     TaskIter it = task_iter(ntasks, NW, 5);
+    // the wave index as a per-lane value (the compiler then keeps the task
+    // indices in vector registers): measured faster for these kernels
+    // (R-MAT 22: 19.0 against 20.3 ms)
+    it.wid = (int)(blockIdx.x / kXcd) * NW + (int)(threadIdx.x >> 6);
     // Rows are software-pipelined: while a row is counted, the next row's
     // index, sizes, first own word per lane and first staged entry per lane
     // (its row of comp(L): offset and word count) are loaded, so a row starts
