@@ -49,6 +49,36 @@ def test_batch_symbolic_numeric():
 
 
 @pytest.mark.parametrize("use_graph,group", [(True, 0), (False, 0), (True, 16)])
+def many_products(count, seed):
+    """Small products of varied shape (some empty), so that waves straddle
+    product boundaries and the product lookup searches more than 64 products."""
+    g = np.random.default_rng(seed)
+    prods = []
+    for t in range(count):
+        m, k, n = (int(x) for x in g.integers(1, 60, 3))
+        if t % 17 == 5:
+            A = synth.Csr(m, k, np.zeros(m + 1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+        else:
+            A = synth.poisson_csr(m, k, float(g.uniform(0.5, 6.0)), 1000 + 2 * t)
+        prods.append((A, synth.poisson_csr(k, n, float(g.uniform(0.5, 8.0)), 1001 + 2 * t)))
+    return prods
+
+
+@pytest.mark.parametrize("count", [65, 300])
+def test_batch_many_products(count):
+    prods = many_products(count, count)
+    As, Bs = to_dev(prods)
+    Cs = mls.batch_symbolic(As, Bs)
+    mls.batch_numeric(As, Bs, Cs)
+    check_all(prods, Cs)
+    plan = mls.BatchPlan(As, Bs, Cs, group_size=8, use_graph=False)
+    for C in Cs:
+        C.values.fill_(float("nan"))
+    plan.run()
+    check_all(prods, Cs)
+
+
+@pytest.mark.parametrize("use_graph,group", [(True, 0), (False, 0), (True, 16)])
 def test_batch_plan_replays(use_graph, group):
     prods = mixed_batch()
     As, Bs = to_dev(prods)
