@@ -20,6 +20,7 @@
 
 #include "common.h"
 #include "launch.h"
+#include "postab.h"
 #include "profile.h"
 
 namespace mls {
@@ -101,9 +102,14 @@ __device__ __forceinline__ void w_lookup_n(const int *key, const double *wv, int
     for (int d = 0; d < D; ++d) w[d] = wv[sl[d] >= 0 ? sl[d] : 0];
 }
 
-// LDS of one row: W_i's hash (key, value), the staged entries of A (first B
-// position, a_ik, their dA sums) and the staged entries' first pairs
-constexpr int bwd_row_bytes(int CAP, int G) { return CAP * 12 + G * 20 + (G + 4) * 4; }
+// LDS of one row: W_i's hash (wide: key and value per slot; packed: a
+// column -> position table and the values by position), the staged entries
+// of A (first B position, a_ik, their dA sums) and the staged entries' first
+// pairs
+constexpr int bwd_row_bytes(int CAP, int G, bool PACK)
+{
+    return (PACK ? CAP * 4 + (CAP / 2) * 8 : CAP * 12) + G * 20 + (G + 4) * 4;
+}
 
 // Waves per workgroup that keep the most waves resident on a CU (160 KB of
 // LDS, 32 waves), given the LDS of one wave.
@@ -175,13 +181,14 @@ __device__ __forceinline__ void bwd_first_b(const Prob &P, BwdFirst &f)
     f.q1 = pb[1];
 }
 
-template <int G, int CAP>
+template <int G, int CAP, bool PACK>
 __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, double *dA, double *dB)
 {
     constexpr int W = kWave / G;
-    constexpr int NW = nw_bwd_best(bwd_row_bytes(CAP, G) * W);
+    constexpr int NW = nw_bwd_best(bwd_row_bytes(CAP, G, PACK) * W);
+    constexpr int WV = PACK ? CAP / 2 : CAP;   // W values per row: by position, or by slot
     __shared__ __attribute__((aligned(16))) int s_key[NW * W * CAP];
-    __shared__ double s_wv[NW * W * CAP];
+    __shared__ double s_wv[NW * W * WV];
     __shared__ double s_pa[NW * W * G];
     __shared__ double s_da[NW * W * G];
     __shared__ int s_pq[NW * W * G];
@@ -193,7 +200,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
     const int slot = lw / G, lane = lw % G;
     const int rs = wave * W + slot;
     int *key = s_key + rs * CAP;
-    double *wv = s_wv + rs * CAP;
+    double *wv = s_wv + rs * WV;
+    PosTab<CAP, true, 4> ptab{(uint32_t *)key};   // PACK: column -> position of W_i
     double *pa = s_pa + rs * G;
     double *da = s_da + rs * G;
     int *pq = s_pq + rs * G;
@@ -238,7 +246,11 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
         int logcap = ilog2_ceil(2 * nw);
         if (logcap < 5) logcap = 5;
         const int cap = 1 << logcap;
-        for (int h = lane; h < cap; h += G) key[h] = -1;
+        if constexpr (PACK) {
+            ptab.clear(cap, lane, G);
+        } else {
+            for (int h = lane; h < cap; h += G) key[h] = -1;
+        }
         // this row's first chunk was located during the previous row
         int ka = f.ka;
         double sa = f.sa;
@@ -255,8 +267,15 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
                 if (e < nw) { jv[u] = wci[ws0 + e]; wj[u] = wval[ws0 + e]; }
             }
 #pragma unroll
-            for (int u = 0; u < kBwdInsDepth; ++u)
-                if (jv[u] >= 0) w_insert(key, wv, logcap, jv[u], wj[u]);
+            for (int u = 0; u < kBwdInsDepth; ++u) {
+                if (jv[u] < 0) continue;
+                if constexpr (PACK) {
+                    ptab.insert(logcap, jv[u], e0 + u * G);
+                    wv[e0 + u * G] = wj[u];
+                } else {
+                    w_insert(key, wv, logcap, jv[u], wj[u]);
+                }
+            }
         }
         bwd_sync();
         bool bad = false;
@@ -356,7 +375,14 @@ __global__ __launch_bounds__(kWG) void k_bwd_lds(Batch b, Sched sc, int bin, dou
                     if (dq[d] >= 0) atomicAdd(dB + dq[d], dv[d]);
                 int sl[kBwdUnroll];
                 double w[kBwdUnroll];
-                w_lookup_n<kBwdUnroll>(key, wv, logcap, jv, sl, w);
+                if constexpr (PACK) {
+                    // positions in W_i's row, then the values by position
+                    ptab.template lookup_n<kBwdUnroll>(logcap, jv, sl);
+#pragma unroll
+                    for (int d = 0; d < kBwdUnroll; ++d) w[d] = wv[sl[d] >= 0 ? sl[d] : 0];
+                } else {
+                    w_lookup_n<kBwdUnroll>(key, wv, logcap, jv, sl, w);
+                }
 #pragma unroll
                 for (int d = 0; d < kBwdUnroll; ++d) asm volatile("" ::"v"(bv[d]));
 #pragma unroll
@@ -581,16 +607,26 @@ static int bwd_grid(K kernel, int threads)
     return cus * per_cu;
 }
 
+template <int G, int CAP, bool PACK>
+static void launch_bwd_variant(const Batch &b, const Sched &sc, int bin, double *dA, double *dB, hipStream_t s)
+{
+    constexpr int W = kWave / G;
+    constexpr int NW = nw_bwd_best(bwd_row_bytes(CAP, G, PACK) * W);
+    static int grid = bwd_grid(k_bwd_lds<G, CAP, PACK>, NW * kWave);
+    static char name[64];
+    if (!name[0]) snprintf(name, sizeof(name), "bwd_lds_G%d_C%d%s", G, CAP, PACK ? "_p" : "");
+    ProfScope ps(name, s);
+    hipLaunchKernelGGL((k_bwd_lds<G, CAP, PACK>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, dA, dB);
+}
+
+// The packed table needs every column index of W below PackBits<CAP>::kMaxCols.
 template <int G, int CAP>
 static void launch_bwd_class(const Batch &b, const Sched &sc, int bin, double *dA, double *dB, hipStream_t s)
 {
-    constexpr int W = kWave / G;
-    constexpr int NW = nw_bwd_best(bwd_row_bytes(CAP, G) * W);
-    static int grid = bwd_grid(k_bwd_lds<G, CAP>, NW * kWave);
-    static char name[64];
-    if (!name[0]) snprintf(name, sizeof(name), "bwd_lds_G%d_C%d", G, CAP);
-    ProfScope ps(name, s);
-    hipLaunchKernelGGL((k_bwd_lds<G, CAP>), dim3(grid), dim3(NW * kWave), 0, s, b, sc, bin, dA, dB);
+    if (b.max_ncols > 0 && (uint32_t)b.max_ncols <= PackBits<CAP>::kMaxCols)
+        launch_bwd_variant<G, CAP, true>(b, sc, bin, dA, dB, s);
+    else
+        launch_bwd_variant<G, CAP, false>(b, sc, bin, dA, dB, s);
 }
 
 void launch_backward(const Batch &b, const Sched &sc, const double *wval, double *dA, double *dB, int G,

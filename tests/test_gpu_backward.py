@@ -216,3 +216,22 @@ def test_forced_class_fused(cls):
     rA, rB, aA, aB = oracle.backward(A, B, W)
     assert np.all(np.abs(dA.cpu().numpy() - rA) <= TOL * aA + 1e-300)
     assert np.all(np.abs(dB.cpu().numpy() - rB) <= TOL * aB + 1e-300)
+
+
+@pytest.mark.parametrize("wide", [0, 1])
+@pytest.mark.parametrize("group", [0, 8, 16, 32, 64])
+def test_fused_table_layouts(wide, group):
+    # packed (column, position) tables with W's values by position, and the
+    # wide (column, value) slots, for every lanes-per-row choice
+    A, B, W = instance(900, 800, 700, 6.0, 9.0, seeds=(61, 62, 63))
+    mls.set_option(mls._abi.OPT_WIDE_TABLE, wide)
+    mls.set_option(mls._abi.OPT_GROUP_SIZE, group)
+    try:
+        dA, dB = mls.backward(mls.DeviceCsr.from_host(A), mls.DeviceCsr.from_host(B), mls.DeviceCsr.from_host(W))
+        torch.cuda.synchronize()
+    finally:
+        mls.set_option(mls._abi.OPT_WIDE_TABLE, 0)
+        mls.set_option(mls._abi.OPT_GROUP_SIZE, 0)
+    rA, rB, aA, aB = oracle.backward(A, B, W)
+    assert np.all(np.abs(dA.cpu().numpy() - rA) <= TOL * aA + 1e-300)
+    assert np.all(np.abs(dB.cpu().numpy() - rB) <= TOL * aB + 1e-300)
