@@ -86,7 +86,7 @@ def frac(nbytes, ms):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("k_numeric.hip", "common.h"):
+    for f in ("k_numeric.hip", "common.h", "postab.h"):
         with open(os.path.join(ROOT, "paper_1804_00695_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
