@@ -233,9 +233,8 @@ struct NumShape {
     // waves per SIMD the kernel is compiled for: the LDS bound, capped so the
     // row pipeline's registers fit without spills (a reload from scratch
     // would wait for every load issued before it): 7 waves (72 VGPRs), 5
-    // (96) for the flattened steps or for batches, 4 (128) for batches with
-    // 32 lanes per row
-    static constexpr int OCC_CAP = (MULTI && G == 32) ? 4 : ((FLAT || MULTI) ? 5 : 7);
+    // (96) for the flattened steps or for batches
+    static constexpr int OCC_CAP = (FLAT || MULTI) ? 5 : 7;
     static constexpr int OCC_R = OCC < OCC_CAP ? OCC : OCC_CAP;
     // the next row's first chunk is prefetched where registers allow (at
     // most 5 waves per SIMD); otherwise a row loads its first chunk when it
